@@ -1,0 +1,274 @@
+/*
+ * oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, obviously-correct complex128 state-vector simulator on the
+ * host.  It is the reference the GPU library is checked against; nothing in
+ * the product path may link, load or call it (only the test suite, the smoke
+ * check and the CPU-baseline leg of the benchmark do).  It shares no code,
+ * header, table or helper with the GPU library.
+ *
+ * Conventions (qHiPSTER, Sec. 2 "Background"):
+ *   - the state of n qubits is 2^n complex doubles stored in index order;
+ *   - qubit q is bit q of the amplitude index, so a gate on qubit k pairs
+ *     amplitudes whose indices differ in bit k, a stride of 2^k apart;
+ *   - a 2x2 gate Q is passed as 8 doubles, row-major (q11, q12, q21, q22),
+ *     each as (re, im), and acts on the column (alpha_{..0_k..}, alpha_{..1_k..})
+ *     as in Eq. (2);
+ *   - the controlled gate of Eq. (3) applies Q to the target only where the
+ *     control bit is 1.
+ *
+ * Arithmetic is IEEE double with C99 complex numbers; the build uses
+ * -fcx-limited-range (textbook complex product) and -ffp-contract=off.
+ * Reductions accumulate in long double (x87 80-bit) in index order.
+ *
+ * OpenMP may split the independent iterations of a loop nest over threads
+ * (Sec. 4.2 "Threading": the nest level with more iterations is the one
+ * parallelised).  Every amplitude is still computed by exactly the formula
+ * below, so the thread count never changes a result.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef double complex cplx;
+
+static int g_threads = 1;
+
+/* Number of OpenMP threads used by the loops below (1 = serial). */
+void oracle_set_threads(int t) { g_threads = t < 1 ? 1 : t; }
+
+int oracle_get_threads(void) { return g_threads; }
+
+static cplx entry(const double* q, int r, int c) {
+  return q[4 * r + 2 * c] + I * q[4 * r + 2 * c + 1];
+}
+
+/* |0...0> (or any computational basis state |idx>). */
+void oracle_init_basis(cplx* a, int n, uint64_t idx) {
+  const uint64_t N = 1ull << n;
+  for (uint64_t i = 0; i < N; i++) a[i] = 0.0;
+  a[idx] = 1.0;
+}
+
+/*
+ * Single-qubit gate on qubit k, Eq. (2), with the loop nest of Fig. 2: the
+ * outer loop walks groups of 2^(k+1) amplitudes, the inner loop walks the
+ * 2^k pairs (i, i + 2^k) inside a group.
+ */
+void oracle_apply_1q(cplx* a, int n, int k, const double* q) {
+  const cplx q11 = entry(q, 0, 0), q12 = entry(q, 0, 1);
+  const cplx q21 = entry(q, 1, 0), q22 = entry(q, 1, 1);
+  const int64_t N = (int64_t)1 << n, s = (int64_t)1 << k;
+  const int64_t outer = N / (2 * s);
+  if (outer >= s) {
+#pragma omp parallel for num_threads(g_threads) if (g_threads > 1) schedule(static)
+    for (int64_t g = 0; g < N; g += 2 * s)
+      for (int64_t i = g; i < g + s; i++) {
+        const cplx x = a[i], y = a[i + s];
+        a[i] = q11 * x + q12 * y;
+        a[i + s] = q21 * x + q22 * y;
+      }
+  } else {
+    for (int64_t g = 0; g < N; g += 2 * s) {
+#pragma omp parallel for num_threads(g_threads) if (g_threads > 1) schedule(static)
+      for (int64_t i = g; i < g + s; i++) {
+        const cplx x = a[i], y = a[i + s];
+        a[i] = q11 * x + q12 * y;
+        a[i + s] = q21 * x + q22 * y;
+      }
+    }
+  }
+}
+
+/*
+ * Controlled-Q with control c and target t, Eq. (3): the Fig. 2 loops over
+ * the target's pairs, skipping every pair whose control bit is 0 (Sec. 3.1).
+ */
+void oracle_apply_cu(cplx* a, int n, int c, int t, const double* q) {
+  const cplx q11 = entry(q, 0, 0), q12 = entry(q, 0, 1);
+  const cplx q21 = entry(q, 1, 0), q22 = entry(q, 1, 1);
+  const int64_t N = (int64_t)1 << n, s = (int64_t)1 << t;
+  const int64_t outer = N / (2 * s);
+  if (outer >= s) {
+#pragma omp parallel for num_threads(g_threads) if (g_threads > 1) schedule(static)
+    for (int64_t g = 0; g < N; g += 2 * s)
+      for (int64_t i = g; i < g + s; i++) {
+        if (((i >> c) & 1) == 0) continue;
+        const cplx x = a[i], y = a[i + s];
+        a[i] = q11 * x + q12 * y;
+        a[i + s] = q21 * x + q22 * y;
+      }
+  } else {
+    for (int64_t g = 0; g < N; g += 2 * s) {
+#pragma omp parallel for num_threads(g_threads) if (g_threads > 1) schedule(static)
+      for (int64_t i = g; i < g + s; i++) {
+        if (((i >> c) & 1) == 0) continue;
+        const cplx x = a[i], y = a[i + s];
+        a[i] = q11 * x + q12 * y;
+        a[i + s] = q21 * x + q22 * y;
+      }
+    }
+  }
+}
+
+/*
+ * Measurement probabilities: full[i] = |a_i|^2 (if full != NULL),
+ * p1[k] = sum of |a_i|^2 over indices with bit k set (the probability of
+ * reading qubit k as 1), and *norm2 = sum of all |a_i|^2.
+ */
+void oracle_probabilities(const cplx* a, int n, double* p1, double* norm2,
+                          double* full) {
+  const uint64_t N = 1ull << n;
+  long double acc[64];
+  long double tot = 0.0L;
+  for (int k = 0; k < n; k++) acc[k] = 0.0L;
+  for (uint64_t i = 0; i < N; i++) {
+    const double re = creal(a[i]), im = cimag(a[i]);
+    const double p = re * re + im * im;
+    if (full) full[i] = p;
+    tot += p;
+    for (int k = 0; k < n; k++)
+      if ((i >> k) & 1) acc[k] += p;
+  }
+  for (int k = 0; k < n; k++) p1[k] = (double)acc[k];
+  if (norm2) *norm2 = (double)tot;
+}
+
+/* <a|b> = sum_i conj(a_i) b_i, accumulated in long double, index order. */
+void oracle_inner(const cplx* a, const cplx* b, int n, double* re, double* im) {
+  const uint64_t N = 1ull << n;
+  long double sr = 0.0L, si = 0.0L;
+  for (uint64_t i = 0; i < N; i++) {
+    const double ar = creal(a[i]), ai = cimag(a[i]);
+    const double br = creal(b[i]), bi = cimag(b[i]);
+    sr += (long double)ar * br + (long double)ai * bi;
+    si += (long double)ar * bi - (long double)ai * br;
+  }
+  *re = (double)sr;
+  *im = (double)si;
+}
+
+/*
+ * Pauli matrices as 2x2 gates in the layout above; code 1 = X, 2 = Y, 3 = Z.
+ * The identity (code 0) is never applied.
+ */
+static void pauli_matrix(int code, double* q) {
+  memset(q, 0, 8 * sizeof(double));
+  if (code == 1) {        /* X = [[0, 1], [1, 0]] */
+    q[2] = 1.0;
+    q[4] = 1.0;
+  } else if (code == 2) { /* Y = [[0, -i], [i, 0]] */
+    q[3] = -1.0;
+    q[5] = 1.0;
+  } else {                /* Z = [[1, 0], [0, -1]] */
+    q[0] = 1.0;
+    q[6] = -1.0;
+  }
+}
+
+/*
+ * out = P a for one Pauli string, given as one code per qubit
+ * (codes[q] in {0 = I, 1 = X, 2 = Y, 3 = Z}): the tensor product is applied
+ * factor by factor as single-qubit gates.
+ */
+void oracle_apply_pauli_string(const cplx* a, int n, const uint8_t* codes,
+                               cplx* out) {
+  const uint64_t N = 1ull << n;
+  double q[8];
+  memcpy(out, a, N * sizeof(cplx));
+  for (int k = 0; k < n; k++) {
+    if (codes[k] == 0) continue;
+    pauli_matrix(codes[k], q);
+    oracle_apply_1q(out, n, k, q);
+  }
+}
+
+/*
+ * <a|H|a> for H = sum_j coeff[j] P_j, codes is nterms x n (row j = P_j).
+ * Each term is Re<a|P_j a> computed from the explicit product P_j a.
+ * Returns 0 on success, -1 if scratch memory could not be allocated.
+ */
+int oracle_expect_pauli(const cplx* a, int n, int nterms, const uint8_t* codes,
+                        const double* coeff, double* out) {
+  const uint64_t N = 1ull << n;
+  cplx* tmp = (cplx*)malloc(N * sizeof(cplx));
+  if (!tmp) return -1;
+  long double e = 0.0L;
+  for (int j = 0; j < nterms; j++) {
+    double re, im;
+    oracle_apply_pauli_string(a, n, codes + (size_t)j * n, tmp);
+    oracle_inner(a, tmp, n, &re, &im);
+    e += (long double)coeff[j] * re;
+  }
+  free(tmp);
+  *out = (double)e;
+  return 0;
+}
+
+/*
+ * out = H a = sum_j coeff[j] P_j a.  Returns 0, or -1 on allocation failure.
+ */
+int oracle_apply_pauli_sum(const cplx* a, int n, int nterms,
+                           const uint8_t* codes, const double* coeff,
+                           cplx* out) {
+  const uint64_t N = 1ull << n;
+  cplx* tmp = (cplx*)malloc(N * sizeof(cplx));
+  if (!tmp) return -1;
+  for (uint64_t i = 0; i < N; i++) out[i] = 0.0;
+  for (int j = 0; j < nterms; j++) {
+    oracle_apply_pauli_string(a, n, codes + (size_t)j * n, tmp);
+    for (uint64_t i = 0; i < N; i++) out[i] += coeff[j] * tmp[i];
+  }
+  free(tmp);
+  return 0;
+}
+
+/*
+ * Gate list, applied in order.  The record layout is that of the circuit
+ * description used throughout (80 bytes): int32 kind, target, control,
+ * param; double mat[8].  Kinds: 0 = general 1-qubit gate (mat), 1 =
+ * controlled gate (mat, control), 2/3/4 = RX/RY/RZ(theta[param]) with
+ * R_P(theta) = exp(-i theta P / 2).
+ */
+typedef struct {
+  int32_t kind, target, control, param;
+  double mat[8];
+} oracle_op;
+
+/* The 2x2 matrix of a rotation, in the 8-double layout used above. */
+void oracle_rotation_matrix(int kind, double theta, double* q) {
+  const double c = cos(theta / 2.0), s = sin(theta / 2.0);
+  memset(q, 0, 8 * sizeof(double));
+  if (kind == 2) {        /* RX = [[c, -i s], [-i s, c]] */
+    q[0] = c; q[3] = -s; q[5] = -s; q[6] = c;
+  } else if (kind == 3) { /* RY = [[c, -s], [s, c]] */
+    q[0] = c; q[2] = -s; q[4] = s; q[6] = c;
+  } else {                /* RZ = diag(exp(-i theta/2), exp(i theta/2)) */
+    q[0] = c; q[1] = -s; q[6] = c; q[7] = s;
+  }
+}
+
+/* Returns 0, or -1 for an unknown kind. */
+int oracle_run(cplx* a, int n, const oracle_op* ops, int nops,
+               const double* theta) {
+  double q[8];
+  for (int g = 0; g < nops; g++) {
+    const oracle_op* op = &ops[g];
+    if (op->kind == 0) {
+      oracle_apply_1q(a, n, op->target, op->mat);
+    } else if (op->kind == 1) {
+      oracle_apply_cu(a, n, op->control, op->target, op->mat);
+    } else if (op->kind >= 2 && op->kind <= 4) {
+      oracle_rotation_matrix(op->kind, theta[op->param], q);
+      oracle_apply_1q(a, n, op->target, q);
+    } else {
+      return -1;
+    }
+  }
+  return 0;
+}

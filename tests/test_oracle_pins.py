@@ -1,0 +1,318 @@
+"""Pins of the CPU oracle against things other than itself: dense Kronecker
+operators (Eq. 1), closed forms, invariants and the paper's printed tables.
+All CPU-only."""
+from __future__ import annotations
+
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import circuits as C
+import oracle as O
+from tests import bruteforce as BF
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rng(seed=0):
+    return np.random.default_rng(seed)
+
+
+# ----------------------------------------------------------- gates (Eq. 2, 3)
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 7])
+def test_1q_matches_kronecker(n):
+    r = rng(n)
+    for k in range(n):
+        q = C.haar_unitary(r)
+        psi = BF.random_state(n, r)
+        ref = BF.kron_1q(n, k, q) @ psi
+        got = O.apply_1q(psi.copy(), n, k, q)
+        assert np.abs(got - ref).max() <= 1e-14
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 6])
+def test_cu_matches_kronecker(n):
+    r = rng(10 + n)
+    for c in range(n):
+        for t in range(n):
+            if c == t:
+                continue
+            q = C.haar_unitary(r)
+            psi = BF.random_state(n, r)
+            ref = BF.kron_cu(n, c, t, q) @ psi
+            got = O.apply_cu(psi.copy(), n, c, t, q)
+            assert np.abs(got - ref).max() <= 1e-14, (c, t)
+
+
+def test_random_circuit_matches_kronecker():
+    n = 6
+    circ = C.random_circuit(n, 60, rng(3))
+    psi = BF.random_state(n, rng(4))
+    ref = psi.copy()
+    for op in circ.ops:
+        q = C.row_to_mat(op["mat"])
+        if op["kind"] == C.OP_U:
+            ref = BF.kron_1q(n, op["target"], q) @ ref
+        else:
+            ref = BF.kron_cu(n, op["control"], op["target"], q) @ ref
+    got = O.run(circ.ops, n, psi=psi.copy())
+    assert np.abs(got - ref).max() <= 1e-13
+
+
+@pytest.mark.parametrize("n", [1, 4, 9, 12])
+def test_hadamard_on_all_gives_uniform(n):
+    psi = O.basis_state(n)
+    for k in range(n):
+        O.apply_1q(psi, n, k, C.H_GATE)
+    assert np.abs(psi - 2.0 ** (-n / 2)).max() <= 4 * n * 2.0 ** (-53) * 2.0 ** (-n / 2) * 4
+
+
+def test_u_then_udagger_returns_input():
+    n = 10
+    circ = C.random_circuit(n, 200, rng(7))
+    psi0 = BF.random_state(n, rng(8))
+    psi = O.run(circ.ops, n, psi=psi0.copy())
+    inv = circ.ops[::-1].copy()
+    for op in inv:
+        op["mat"] = C.mat_to_row(C.row_to_mat(op["mat"]).conj().T)
+    O.run(inv, n, psi=psi)
+    assert np.abs(psi - psi0).max() <= 1e-13
+
+
+def test_norm_preserved():
+    n = 12
+    circ = C.random_circuit(n, 300, rng(9))
+    psi = O.run(circ.ops, n)
+    assert abs(np.vdot(psi, psi).real - 1.0) <= 1e-13
+
+
+@pytest.mark.parametrize("c,t", [(0, 1), (1, 0), (3, 7), (7, 2), (9, 0)])
+def test_cnot_is_exact_index_permutation(c, t):
+    n = 10
+    psi = BF.random_state(n, rng(c * 31 + t))
+    got = O.apply_cu(psi.copy(), n, c, t, C.X_GATE)
+    idx = np.arange(1 << n)
+    perm = np.where((idx >> c) & 1, idx ^ (1 << t), idx)
+    assert np.array_equal(got, psi[perm])
+
+
+def test_identity_cu_is_noop():
+    n = 8
+    psi = BF.random_state(n, rng(5))
+    got = O.apply_cu(psi.copy(), n, 2, 5, C.I_GATE)
+    assert np.array_equal(got, psi)
+
+
+def _bitrev(z, n):
+    return int(format(z, "0%db" % n)[::-1], 2) if n else 0
+
+
+def qft_closed_form(n, x):
+    """QFT|x> without the output reversal: amplitude of |z> is
+    2^(-n/2) exp(2 pi i (x * rev_n(z) mod 2^n) / 2^n), exponent reduced in
+    integers first."""
+    N = 1 << n
+    z = np.arange(N)
+    rev = np.array([_bitrev(v, n) for v in z], dtype=np.int64)
+    ph = (x * rev) % N
+    return np.exp(2j * np.pi * ph / N) / math.sqrt(N)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8])
+def test_qft_basis_state_closed_form(n):
+    circ = C.qft_circuit(n)
+    for x in range(1 << n):
+        psi = O.run(circ.ops, n, psi=O.basis_state(n, x))
+        assert np.abs(psi - qft_closed_form(n, x)).max() <= 1e-13, x
+
+
+def test_iqft_inverts_qft():
+    n = 7
+    psi0 = BF.random_state(n, rng(11))
+    psi = O.run(C.qft_circuit(n).ops, n, psi=psi0.copy())
+    O.run(C.iqft_circuit(n).ops, n, psi=psi)
+    assert np.abs(psi - psi0).max() <= 1e-13
+
+
+def test_oracle_threads_do_not_change_results():
+    n = 14
+    circ = C.random_circuit(n, 50, rng(12))
+    O.set_threads(1)
+    a = O.run(circ.ops, n)
+    O.set_threads(4)
+    try:
+        b = O.run(circ.ops, n)
+    finally:
+        O.set_threads(1)
+    assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------- probabilities
+
+def test_probabilities_bruteforce():
+    n = 9
+    psi = BF.random_state(n, rng(13))
+    p1, nrm, full = O.probabilities(psi, n, full=True)
+    pf = np.abs(psi) ** 2
+    idx = np.arange(1 << n)
+    for k in range(n):
+        assert abs(p1[k] - pf[(idx >> k) & 1 == 1].sum()) <= 1e-15
+    assert np.abs(full - pf).max() <= 1e-16
+    assert abs(nrm - 1.0) <= 1e-14
+
+
+def test_probabilities_special_states():
+    n = 10
+    psi = O.basis_state(n)
+    for k in range(n):
+        O.apply_1q(psi, n, k, C.H_GATE)
+    p1, nrm, _ = O.probabilities(psi, n)
+    assert np.abs(p1 - 0.5).max() <= 1e-14 and abs(nrm - 1) <= 1e-14
+    x = 0b1011001101
+    p1, nrm, full = O.probabilities(O.basis_state(n, x), n, full=True)
+    assert [int(v) for v in p1] == [(x >> k) & 1 for k in range(n)]
+    assert full[x] == 1.0 and full.sum() == 1.0
+
+
+# ----------------------------------------------------------------- rotations
+
+@pytest.mark.parametrize("kind,p", [(C.OP_RX, 1), (C.OP_RY, 2), (C.OP_RZ, 3)])
+def test_rotation_matrix_is_exponential_of_generator(kind, p):
+    for th in (0.0, 0.3, -1.7, 2.5, 6.1):
+        ref = scipy.linalg.expm(-0.5j * th * BF.PAULI[p])
+        assert np.abs(O.rotation_matrix(kind, th) - ref).max() <= 1e-15
+
+
+# ----------------------------------------------------------- Pauli expectation
+
+@pytest.mark.parametrize("n", [1, 3, 6])
+def test_expect_pauli_kronecker(n):
+    r = rng(20 + n)
+    ham = C.random_pauli_sum(n, 12, r)
+    psi = BF.random_state(n, r)
+    hmat = BF.kron_hamiltonian(ham.codes, ham.coeff)
+    ref = np.vdot(psi, hmat @ psi).real
+    assert abs(O.expect_pauli(psi, n, ham.codes, ham.coeff) - ref) <= 1e-13
+    lam = O.apply_pauli_sum(psi, n, ham.codes, ham.coeff)
+    assert np.abs(lam - hmat @ psi).max() <= 1e-13
+
+
+def test_expect_product_state_closed_forms():
+    n = 5
+    for a, b in [(0.4, 1.1), (2.9, -0.7), (5.5, 3.0)]:
+        for q in range(n):
+            ops = np.concatenate([C.op_rot(C.OP_RY, q, 0), C.op_rot(C.OP_RZ, q, 1)])
+            psi = O.run(ops, n, np.array([a, b]))
+            codes = np.zeros((3, n), dtype=np.uint8)
+            codes[0, q], codes[1, q], codes[2, q] = 3, 1, 2
+            ez, ex, ey = (O.expect_pauli(psi, n, codes[i:i + 1], [1.0]) for i in range(3))
+            assert abs(ez - math.cos(a)) <= 1e-14
+            assert abs(ex - math.sin(a) * math.cos(b)) <= 1e-14
+            assert abs(ey - math.sin(a) * math.sin(b)) <= 1e-14
+
+
+# ------------------------------------------------------------------ gradients
+
+def test_param_shift_closed_form_single_qubit():
+    # E(a, b) = <X> after RY(a) RZ(b) |0> = sin a cos b.
+    ops = np.concatenate([C.op_rot(C.OP_RY, 0, 0), C.op_rot(C.OP_RZ, 0, 1)])
+    codes = np.array([[1]], dtype=np.uint8)
+    for a, b in [(0.3, 0.2), (1.9, -2.2), (4.0, 5.0)]:
+        th = np.array([a, b])
+        g = O.grad_param_shift(ops, 1, th, codes, [1.0])
+        assert abs(g[0] - math.cos(a) * math.cos(b)) <= 1e-14
+        assert abs(g[1] + math.sin(a) * math.sin(b)) <= 1e-14
+
+
+def test_param_shift_matches_central_fd():
+    n = 4
+    circ, ham = C.workload_ansatz(n, layers=2, nterms=10, seed=99)
+    gps = O.grad_param_shift(circ.ops, n, circ.theta, ham.codes, ham.coeff)
+    gfd = O.grad_central_fd(circ.ops, n, circ.theta, ham.codes, ham.coeff)
+    assert np.abs(gps - gfd).max() <= 1e-6 * max(np.abs(gfd).max(), 1.0)
+
+
+def test_param_shift_dense_matrix_derivative():
+    # Differentiate E through dense matrices with the analytic generator
+    # dU/dtheta = -(i/2) P U, independent of the shift rule.
+    n = 3
+    circ, ham = C.workload_ansatz(n, layers=2, nterms=6, seed=5)
+    hmat = BF.kron_hamiltonian(ham.codes, ham.coeff)
+    mats = []
+    for op in circ.ops:
+        if op["kind"] == C.OP_CU:
+            mats.append(BF.kron_cu(n, op["control"], op["target"], C.row_to_mat(op["mat"])))
+        else:
+            p = {C.OP_RX: 1, C.OP_RY: 2, C.OP_RZ: 3}[int(op["kind"])]
+            u = scipy.linalg.expm(-0.5j * circ.theta[op["param"]] * BF.PAULI[p])
+            mats.append(BF.kron_1q(n, op["target"], u))
+    psi0 = np.zeros(1 << n, dtype=np.complex128)
+    psi0[0] = 1
+    ref = np.zeros(circ.nparams)
+    for g, op in enumerate(circ.ops):
+        if op["kind"] == C.OP_CU:
+            continue
+        p = {C.OP_RX: 1, C.OP_RY: 2, C.OP_RZ: 3}[int(op["kind"])]
+        v = psi0
+        dv = None
+        for h, m in enumerate(mats):
+            v = m @ v
+            if h == g:
+                dv = -0.5j * BF.kron_1q(n, op["target"], BF.PAULI[p]) @ v
+            elif dv is not None:
+                dv = m @ dv
+        ref[op["param"]] += 2 * np.vdot(v, hmat @ dv).real
+    got = O.grad_param_shift(circ.ops, n, circ.theta, ham.codes, ham.coeff)
+    assert np.abs(got - ref).max() <= 1e-12
+
+
+def test_rz_on_basis_state_has_zero_gradient():
+    n = 3
+    ops = C.op_rot(C.OP_RZ, 1, 0)
+    codes = np.array([[3, 3, 0], [0, 1, 3]], dtype=np.uint8)
+    g = O.grad_param_shift(ops, n, np.array([0.77]), codes, [1.0, 0.5])
+    assert g[0] == 0.0
+
+
+# ------------------------------------------------------------- paper tables
+
+def _rows(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return [ln.split() for ln in f if ln.strip() and not ln.startswith("#")]
+
+
+def test_qft_gate_counts_match_table3():
+    rows = _rows("table3_qft.txt")
+    assert len(rows) == 12
+    for n, ngates, total, per_gate in rows:
+        assert len(C.qft_circuit(int(n))) == int(ngates) == int(n) * (int(n) + 1) // 2
+        # the printed per-gate time is total / ngates rounded to 0.01 s
+        assert abs(float(total) / int(ngates) - float(per_gate)) <= 0.006
+
+
+def test_workload_generators_are_seeded():
+    a = C.workload_gates(8, 30)
+    b = C.workload_gates(8, 30)
+    assert a.ops.tobytes() == b.ops.tobytes()
+    for op in a.ops:
+        q = C.row_to_mat(op["mat"])
+        assert np.abs(q @ q.conj().T - np.eye(2)).max() <= 1e-14
+        if op["kind"] == C.OP_CU:
+            assert op["control"] != op["target"]
+    circ, ham = C.workload_ansatz(6, 3, 20)
+    assert circ.nparams == 2 * 6 * 3 and len(circ) == 3 * (3 * 6 - 1)
+    w = (ham.codes > 0).sum(axis=1)
+    assert w.min() >= 1 and w.max() <= 4
+
+
+def test_inner_product_matches_vdot():
+    n = 8
+    a, b = BF.random_state(n, rng(30)), BF.random_state(n, rng(31))
+    got = O.inner(a, b, n)
+    ref = np.vdot(a, b)
+    assert abs(got.real - ref.real) <= 1e-15 and abs(got.imag - ref.imag) <= 1e-15
+    assert abs(O.inner(a, 1j * a, n) - 1j) <= 1e-15
