@@ -1,0 +1,210 @@
+/*
+ * qs.h -- C ABI of libqs, a state-vector quantum circuit simulator for one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The problem statement follows qHiPSTER (Smelyanskiy, Sawaya, Aspuru-Guzik,
+ * arXiv:1601.07195), Sec. 2 "Background":
+ *   - an n-qubit pure state is 2^n complex amplitudes stored densely in index
+ *     order; qubit q is bit q of the amplitude index (so a gate on qubit k
+ *     pairs amplitudes 2^k apart);
+ *   - a single-qubit gate applies a 2x2 matrix Q to every such pair, Eq. (2);
+ *   - a controlled gate applies Q to target t only where control bit c is 1,
+ *     Eq. (3).
+ *
+ * Conventions shared by every entry point
+ *   - Amplitudes are interleaved (re, im).  dtype QS_C128 stores two doubles
+ *     per amplitude (16 B), QS_C64 two floats (8 B).  Every reduction
+ *     (probabilities, norms, expectation values, gradients) accumulates in
+ *     double precision on the GPU for both dtypes.
+ *   - A 2x2 gate is 8 doubles, row-major q11, q12, q21, q22, each as (re, im);
+ *     it maps (alpha_{..0..}, alpha_{..1..}) to Q (alpha_{..0..}, alpha_{..1..}).
+ *     Unitarity is the caller's responsibility (it is never checked).
+ *   - Rotations are R_P(theta) = exp(-i theta P / 2) for P in {X, Y, Z}.
+ *   - Pauli strings are given by two bit masks: bit q of x is set where the
+ *     factor on qubit q is X or Y, bit q of z where it is Z or Y.
+ *   - "dev" pointers are device memory on the state's GPU, owned by the
+ *     caller (e.g. a torch tensor); "host" pointers are ordinary host memory,
+ *     read or written before the call returns.
+ *   - All work is queued on the stream bound to the state (see qs_create).
+ *     Calls that return only device results are asynchronous; calls that
+ *     return host values (probabilities, expectation, energy, gradient)
+ *     synchronise that stream before returning.
+ *   - Every argument is validated on the host before any GPU work is queued;
+ *     on error nothing is launched and the state is unchanged.  The return
+ *     value is QS_OK (0) or a negative QS_E* code; qs_last_error() gives a
+ *     message for the calling thread's most recent failure.
+ *   - A state handle must not be used from two host threads at once.
+ */
+#ifndef QS_H_
+#define QS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define QS_OK 0
+#define QS_EINVAL (-1)      /* bad argument (index out of range, NULL, c == t, ...) */
+#define QS_ENOMEM (-2)      /* device or host allocation failed */
+#define QS_EHIP (-3)        /* a HIP runtime call or kernel launch failed */
+#define QS_ENODEV (-4)      /* no usable gfx950 device */
+#define QS_ERANGE (-5)      /* size out of range (n too large, buffer too small) */
+
+/* Amplitude types. */
+#define QS_C64 1            /* complex64: float re, float im */
+#define QS_C128 2           /* complex128: double re, double im */
+
+/* Largest n per dtype: the state must fit one MI355X (288 GB HBM3E). */
+#define QS_MAX_QUBITS_C128 33
+#define QS_MAX_QUBITS_C64 34
+
+/* Gate kinds of a qs_op. */
+#define QS_OP_U 0           /* general 1-qubit gate `mat` on `target` (Eq. 2) */
+#define QS_OP_CU 1          /* controlled `mat`: control `control`, target `target` (Eq. 3) */
+#define QS_OP_RX 2          /* exp(-i theta X / 2) on `target`, theta = theta[param] */
+#define QS_OP_RY 3          /* exp(-i theta Y / 2) */
+#define QS_OP_RZ 4          /* exp(-i theta Z / 2) */
+
+/* One gate of a circuit (80 bytes, no padding). */
+typedef struct qs_op {
+  int32_t kind;     /* QS_OP_* */
+  int32_t target;   /* 0 <= target < n */
+  int32_t control;  /* QS_OP_CU: 0 <= control < n, control != target; else ignored */
+  int32_t param;    /* rotations: index into theta; else ignored */
+  double mat[8];    /* QS_OP_U / QS_OP_CU: the 2x2 gate; else ignored */
+} qs_op;
+
+typedef struct qs_state qs_state; /* opaque handle, owned by the library */
+
+/* Library version as 10000*major + 100*minor + patch. */
+int qs_version(void);
+
+/* Static text for a status code. */
+const char* qs_strerror(int code);
+
+/* Message for the calling thread's last failed call ("" if none). */
+const char* qs_last_error(void);
+
+/*
+ * Bind an n-qubit state to caller-owned device memory (Sec. 2: 2^n
+ * amplitudes of `dtype`, i.e. 2^n * 16 or 2^n * 8 bytes).
+ *   n        1 <= n <= QS_MAX_QUBITS_C128 (QS_C128) or QS_MAX_QUBITS_C64 (QS_C64)
+ *   dtype    QS_C64 or QS_C128
+ *   dev_ptr  device pointer, 256-byte aligned, at least 2^n amplitudes; the
+ *            caller keeps ownership and must keep it alive until qs_destroy
+ *   bytes    size of the buffer at dev_ptr (QS_ERANGE if too small)
+ *   stream   hipStream_t to queue work on (NULL = the null stream)
+ *   out      receives the handle
+ * The amplitudes are not touched (use qs_init_basis).  No GPU work is done
+ * here; the device is the one current on the calling thread.
+ * Errors: QS_EINVAL (NULL out/dev_ptr, bad dtype, misaligned), QS_ERANGE,
+ * QS_ENOMEM (handle allocation), QS_ENODEV (no device current).
+ */
+int qs_create(int n, int dtype, void* dev_ptr, size_t bytes, void* stream,
+              qs_state** out);
+
+/* Release the handle and the library's scratch memory (not dev_ptr).
+ * Waits for the state's queued work first.  NULL is accepted. */
+int qs_destroy(qs_state* s);
+
+/* Queue later work of this state on another hipStream_t. */
+int qs_set_stream(qs_state* s, void* stream);
+
+/* State = computational basis state |index> (index < 2^n); |0...0> for 0. */
+int qs_init_basis(qs_state* s, uint64_t index);
+
+/*
+ * Single-qubit gate on qubit k, in place: Eq. (2) of Sec. 2, i.e. Q applied
+ * to every pair (i, i + 2^k) with bit k of i clear (the loop nest of
+ * Fig. 2).  q: host, 8 doubles as above.  Errors: QS_EINVAL (k out of range,
+ * NULL), QS_EHIP.
+ */
+int qs_apply_1q(qs_state* s, int k, const double* q);
+
+/*
+ * Controlled gate, in place: Eq. (3) of Sec. 2, i.e. Q applied to the pairs
+ * (i, i + 2^t) whose control bit c is 1; the other amplitudes are neither
+ * read nor written.  Errors: QS_EINVAL (c or t out of range, c == t, NULL).
+ */
+int qs_apply_cu(qs_state* s, int c, int t, const double* q);
+
+/*
+ * Apply a gate list in order, in place.  Consecutive gates may be fused
+ * into one pass over the state that keeps a block of amplitudes on chip
+ * while several gates are applied to it (cache blocking by gate fusion,
+ * Sec. 4.4 and Fig. 4); gates acting on disjoint qubits may be reordered
+ * past each other.  The result equals applying the gates one by one up to
+ * floating-point rounding.
+ *   ops     host array of nops records
+ *   theta   host array of nparams angles (may be NULL if no rotations)
+ *   flags   QS_RUN_* bits
+ * Errors: QS_EINVAL for any malformed op (checked before any launch).
+ */
+#define QS_RUN_NO_FUSION 1  /* one streaming pass per gate (no cache blocking) */
+int qs_run(qs_state* s, const qs_op* ops, int nops, const double* theta,
+           int nparams, int flags);
+
+/*
+ * Measurement probabilities of the state (not part of the paper; the
+ * per-qubit marginals of |alpha_i|^2):
+ *   p1     host, n doubles or NULL: p1[k] = sum over i with bit k set of |alpha_i|^2
+ *   norm2  host, 1 double or NULL: sum of all |alpha_i|^2
+ *   full   dev, 2^n doubles or NULL: full[i] = |alpha_i|^2
+ *   full_bytes  size of `full` (QS_ERANGE if smaller than 2^n doubles)
+ * Sums are double, accumulated in a fixed order (bitwise reproducible run to
+ * run).  Synchronises the stream when p1 or norm2 is given.
+ */
+int qs_probabilities(qs_state* s, double* p1, double* norm2, void* full,
+                     size_t full_bytes);
+
+/*
+ * Expectation value <psi|H|psi> of H = sum_j coeff[j] P_j, P_j the Pauli
+ * string (x[j], z[j]) (not part of the paper).  The result is not divided
+ * by the norm.  x, z, coeff: host arrays of nterms (nterms >= 0; every mask
+ * must lie within the n qubits).  out: host, 1 double.  Synchronises.
+ */
+int qs_expect_pauli(qs_state* s, int nterms, const uint64_t* x,
+                    const uint64_t* z, const double* coeff, double* out);
+
+/*
+ * dst = H src for H = sum_j coeff[j] P_j (both states of the same n and
+ * dtype, distinct memory).  Asynchronous.
+ */
+int qs_apply_pauli_sum(qs_state* src, qs_state* dst, int nterms,
+                       const uint64_t* x, const uint64_t* z,
+                       const double* coeff);
+
+/*
+ * Energy and gradient of E(theta) = <psi(theta)|H|psi(theta)>, psi(theta)
+ * = U_N ... U_1 |psi_0>, by the adjoint method (one reverse sweep over two
+ * state vectors; Jones & Gacon, arXiv:2009.02823).  Not part of the paper.
+ *   s       on entry psi_0 (or psi(theta), see flags); the forward sweep takes
+ *           it to psi(theta) and the reverse sweep takes it back, so on
+ *           return it holds psi_0 (up to rounding)
+ *   ops, nops, theta, nparams   the circuit as for qs_run; rotations carry
+ *           the parameters, every other gate is fixed
+ *   nterms, x, z, coeff         H as for qs_expect_pauli
+ *   lambda  second state (same n, dtype), used as workspace; overwritten
+ *   flags   QS_ADJ_* bits: with QS_ADJ_STATE_IS_FINAL the state already
+ *           holds psi(theta) (e.g. left by qs_run) and the forward sweep is
+ *           skipped
+ *   energy  host, 1 double (may be NULL)
+ *   grad    host, nparams doubles (dE/dtheta[p], summed over every rotation
+ *           that uses parameter p)
+ * The gradient is accumulated in double precision for both dtypes, in a
+ * fixed order.  Synchronises.
+ */
+#define QS_ADJ_STATE_IS_FINAL 1
+int qs_grad_adjoint(qs_state* s, const qs_op* ops, int nops,
+                    const double* theta, int nparams, int nterms,
+                    const uint64_t* x, const uint64_t* z, const double* coeff,
+                    qs_state* lambda, int flags, double* energy, double* grad);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QS_H_ */

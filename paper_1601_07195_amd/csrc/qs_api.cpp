@@ -1,0 +1,359 @@
+// qs_api.cpp -- the C ABI of libqs: argument validation, state handles,
+// small-buffer management and dispatch to the kernel launchers.
+//
+// Every entry point validates all of its arguments on the host before the
+// first HIP call, so a rejected call queues nothing.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "qs_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int done(const qs::Status& s) {
+  if (s.good()) return QS_OK;
+  return fail(s.code, s.msg);
+}
+
+int max_qubits(int dtype) { return dtype == QS_C128 ? QS_MAX_QUBITS_C128 : QS_MAX_QUBITS_C64; }
+
+bool valid_state(const qs_state* s) { return s && s->impl.ptr && s->impl.n > 0; }
+
+}  // namespace
+
+namespace qs {
+
+Status ensure_dev(StateImpl* s, DevBuf& b, size_t bytes) {
+  if (b.bytes >= bytes) return Status::ok();
+  if (b.ptr) {
+    // Earlier queued kernels may still read the old buffer.
+    Status st = hip_status(hipStreamSynchronize(s->stream), "sync before regrow");
+    if (!st.good()) return st;
+    (void)hipFree(b.ptr);
+    b.ptr = nullptr;
+    b.bytes = 0;
+  }
+  size_t want = 4096;
+  while (want < bytes) want <<= 1;
+  void* p = nullptr;
+  if (hipMalloc(&p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    Status st;
+    st.code = QS_ENOMEM;
+    st.msg = "device scratch allocation of " + std::to_string(want) + " bytes failed";
+    return st;
+  }
+  b.ptr = p;
+  b.bytes = want;
+  return Status::ok();
+}
+
+Status ensure_result_host(StateImpl* s, size_t bytes) {
+  if (s->result_bytes >= bytes) return Status::ok();
+  if (s->result_host) (void)hipHostFree(s->result_host);
+  s->result_host = nullptr;
+  s->result_bytes = 0;
+  size_t want = 4096;
+  while (want < bytes) want <<= 1;
+  void* p = nullptr;
+  if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    Status st;
+    st.code = QS_ENOMEM;
+    st.msg = "pinned host allocation failed";
+    return st;
+  }
+  s->result_host = (double*)p;
+  s->result_bytes = want;
+  return Status::ok();
+}
+
+Status upload_table(StateImpl* s, const void* src, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  Status st;
+  if (s->stage.pending) {
+    st = hip_status(hipEventSynchronize(s->stage.done), "staging wait");
+    if (!st.good()) return st;
+    s->stage.pending = false;
+  }
+  if (s->stage.bytes < bytes) {
+    if (s->stage.host) (void)hipHostFree(s->stage.host);
+    s->stage.host = nullptr;
+    s->stage.bytes = 0;
+    size_t want = 4096;
+    while (want < bytes) want <<= 1;
+    if (hipHostMalloc(&s->stage.host, want, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      st.code = QS_ENOMEM;
+      st.msg = "pinned staging allocation failed";
+      return st;
+    }
+    s->stage.bytes = want;
+  }
+  if (!s->stage.done) {
+    st = hip_status(hipEventCreateWithFlags(&s->stage.done, hipEventDisableTiming), "event");
+    if (!st.good()) return st;
+  }
+  st = ensure_dev(s, s->table, bytes);
+  if (!st.good()) return st;
+  if (src) memcpy(s->stage.host, src, bytes);
+  st = hip_status(hipMemcpyAsync(s->table.ptr, s->stage.host, bytes, hipMemcpyHostToDevice,
+                                 s->stream), "table upload");
+  if (!st.good()) return st;
+  st = hip_status(hipEventRecord(s->stage.done, s->stream), "event record");
+  if (!st.good()) return st;
+  s->stage.pending = true;
+  return Status::ok();
+}
+
+// Matrix of a rotation R_P(theta) = exp(-i theta P / 2), 8-double layout.
+static void rotation(int kind, double theta, double* m) {
+  const double c = cos(0.5 * theta), sn = sin(0.5 * theta);
+  for (int e = 0; e < 8; ++e) m[e] = 0.0;
+  if (kind == QS_OP_RX) {  // [[c, -i s], [-i s, c]]
+    m[0] = c; m[3] = -sn; m[5] = -sn; m[6] = c;
+  } else if (kind == QS_OP_RY) {  // [[c, -s], [s, c]]
+    m[0] = c; m[2] = -sn; m[4] = sn; m[6] = c;
+  } else {  // RZ: diag(e^{-i theta/2}, e^{i theta/2})
+    m[0] = c; m[1] = -sn; m[6] = c; m[7] = sn;
+  }
+}
+
+Status normalize_ops(int n, const qs_op* ops, int nops, const double* theta, int nparams,
+                     std::vector<XGate>* out) {
+  out->clear();
+  out->reserve(nops);
+  Status bad;
+  bad.code = QS_EINVAL;
+  for (int g = 0; g < nops; ++g) {
+    const qs_op& op = ops[g];
+    XGate x;
+    x.kind = op.kind;
+    x.target = op.target;
+    x.control = -1;
+    x.param = -1;
+    if (op.target < 0 || op.target >= n) {
+      bad.msg = "op " + std::to_string(g) + ": target " + std::to_string(op.target) + " out of range";
+      return bad;
+    }
+    switch (op.kind) {
+      case QS_OP_U:
+        memcpy(x.m, op.mat, sizeof(x.m));
+        break;
+      case QS_OP_CU:
+        if (op.control < 0 || op.control >= n || op.control == op.target) {
+          bad.msg = "op " + std::to_string(g) + ": bad control " + std::to_string(op.control);
+          return bad;
+        }
+        x.control = op.control;
+        memcpy(x.m, op.mat, sizeof(x.m));
+        break;
+      case QS_OP_RX:
+      case QS_OP_RY:
+      case QS_OP_RZ:
+        if (!theta || op.param < 0 || op.param >= nparams) {
+          bad.msg = "op " + std::to_string(g) + ": parameter index " + std::to_string(op.param) +
+                    " out of range";
+          return bad;
+        }
+        x.param = op.param;
+        rotation(op.kind, theta[op.param], x.m);
+        break;
+      default:
+        bad.msg = "op " + std::to_string(g) + ": unknown kind " + std::to_string(op.kind);
+        return bad;
+    }
+    out->push_back(x);
+  }
+  return Status::ok();
+}
+
+}  // namespace qs
+
+using qs::Status;
+
+extern "C" {
+
+int qs_version(void) { return 10000; }
+
+const char* qs_strerror(int code) {
+  switch (code) {
+    case QS_OK: return "success";
+    case QS_EINVAL: return "invalid argument";
+    case QS_ENOMEM: return "out of memory";
+    case QS_EHIP: return "HIP runtime error";
+    case QS_ENODEV: return "no usable GPU device";
+    case QS_ERANGE: return "size out of range";
+    default: return "unknown status";
+  }
+}
+
+const char* qs_last_error(void) { return g_last_error.c_str(); }
+
+int qs_create(int n, int dtype, void* dev_ptr, size_t bytes, void* stream, qs_state** out) {
+  if (!out) return fail(QS_EINVAL, "qs_create: out is NULL");
+  *out = nullptr;
+  if (dtype != QS_C64 && dtype != QS_C128) return fail(QS_EINVAL, "qs_create: bad dtype");
+  if (n < 1 || n > max_qubits(dtype))
+    return fail(QS_ERANGE, "qs_create: n=" + std::to_string(n) + " outside 1.." +
+                               std::to_string(max_qubits(dtype)));
+  if (!dev_ptr) return fail(QS_EINVAL, "qs_create: dev_ptr is NULL");
+  if (((uintptr_t)dev_ptr) & 255) return fail(QS_EINVAL, "qs_create: dev_ptr not 256-byte aligned");
+  const size_t need = ((size_t)1 << n) * qs::amp_bytes(dtype);
+  if (bytes < need)
+    return fail(QS_ERANGE, "qs_create: buffer of " + std::to_string(bytes) + " bytes < " +
+                               std::to_string(need));
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(QS_ENODEV, "qs_create: no HIP device");
+  }
+  qs_state* s = new (std::nothrow) qs_state();
+  if (!s) return fail(QS_ENOMEM, "qs_create: handle allocation failed");
+  s->impl.n = n;
+  s->impl.dtype = dtype;
+  s->impl.ptr = dev_ptr;
+  s->impl.bytes = bytes;
+  s->impl.stream = (hipStream_t)stream;
+  s->impl.device = dev;
+  *out = s;
+  return QS_OK;
+}
+
+int qs_destroy(qs_state* s) {
+  if (!s) return QS_OK;
+  qs::StateImpl& m = s->impl;
+  int rc = QS_OK;
+  if (hipStreamSynchronize(m.stream) != hipSuccess) {
+    (void)hipGetLastError();
+    rc = fail(QS_EHIP, "qs_destroy: stream synchronisation failed");
+  }
+  if (m.red.ptr) (void)hipFree(m.red.ptr);
+  if (m.table.ptr) (void)hipFree(m.table.ptr);
+  if (m.stage.host) (void)hipHostFree(m.stage.host);
+  if (m.stage.done) (void)hipEventDestroy(m.stage.done);
+  if (m.result_host) (void)hipHostFree(m.result_host);
+  delete s;
+  return rc;
+}
+
+int qs_set_stream(qs_state* s, void* stream) {
+  if (!valid_state(s)) return fail(QS_EINVAL, "qs_set_stream: bad state");
+  // Work queued on the old stream must finish before the new stream reuses
+  // the handle's scratch buffers.
+  Status st = qs::hip_status(hipStreamSynchronize(s->impl.stream), "qs_set_stream sync");
+  if (!st.good()) return done(st);
+  s->impl.stream = (hipStream_t)stream;
+  return QS_OK;
+}
+
+int qs_init_basis(qs_state* s, uint64_t index) {
+  if (!valid_state(s)) return fail(QS_EINVAL, "qs_init_basis: bad state");
+  if (index >= (1ull << s->impl.n)) return fail(QS_EINVAL, "qs_init_basis: index >= 2^n");
+  return done(qs::launch_init_basis(&s->impl, index));
+}
+
+int qs_apply_1q(qs_state* s, int k, const double* q) {
+  if (!valid_state(s)) return fail(QS_EINVAL, "qs_apply_1q: bad state");
+  if (!q) return fail(QS_EINVAL, "qs_apply_1q: q is NULL");
+  if (k < 0 || k >= s->impl.n) return fail(QS_EINVAL, "qs_apply_1q: target out of range");
+  return done(qs::launch_apply_1q(&s->impl, k, q));
+}
+
+int qs_apply_cu(qs_state* s, int c, int t, const double* q) {
+  if (!valid_state(s)) return fail(QS_EINVAL, "qs_apply_cu: bad state");
+  if (!q) return fail(QS_EINVAL, "qs_apply_cu: q is NULL");
+  const int n = s->impl.n;
+  if (c < 0 || c >= n || t < 0 || t >= n) return fail(QS_EINVAL, "qs_apply_cu: qubit out of range");
+  if (c == t) return fail(QS_EINVAL, "qs_apply_cu: control equals target");
+  return done(qs::launch_apply_cu(&s->impl, c, t, q));
+}
+
+int qs_run(qs_state* s, const qs_op* ops, int nops, const double* theta, int nparams, int flags) {
+  if (!valid_state(s)) return fail(QS_EINVAL, "qs_run: bad state");
+  if (nops < 0 || (nops > 0 && !ops)) return fail(QS_EINVAL, "qs_run: bad op list");
+  if (nparams < 0) return fail(QS_EINVAL, "qs_run: nparams < 0");
+  if (flags & ~QS_RUN_NO_FUSION) return fail(QS_EINVAL, "qs_run: unknown flags");
+  std::vector<qs::XGate> gates;
+  Status st = qs::normalize_ops(s->impl.n, ops, nops, theta, nparams, &gates);
+  if (!st.good()) return done(st);
+  return done(qs::run_gates(&s->impl, gates, flags));
+}
+
+static int check_terms(const char* who, int nterms, const uint64_t* x, const uint64_t* z,
+                       const double* coeff) {
+  if (nterms < 0) return fail(QS_EINVAL, std::string(who) + ": nterms < 0");
+  if (nterms > 0 && (!x || !z || !coeff)) return fail(QS_EINVAL, std::string(who) + ": NULL term array");
+  return QS_OK;
+}
+
+int qs_probabilities(qs_state* s, double* p1, double* norm2, void* full, size_t full_bytes) {
+  if (!valid_state(s)) return fail(QS_EINVAL, "qs_probabilities: bad state");
+  if (full) {
+    if (((uintptr_t)full) & 7) return fail(QS_EINVAL, "qs_probabilities: full not 8-byte aligned");
+    if (full_bytes < (((size_t)1) << s->impl.n) * sizeof(double))
+      return fail(QS_ERANGE, "qs_probabilities: full buffer too small");
+  }
+  if (!p1 && !norm2 && !full) return QS_OK;
+  return done(qs::launch_probabilities(&s->impl, p1, norm2, (double*)full));
+}
+
+int qs_expect_pauli(qs_state* s, int nterms, const uint64_t* x, const uint64_t* z,
+                    const double* coeff, double* out) {
+  if (!valid_state(s)) return fail(QS_EINVAL, "qs_expect_pauli: bad state");
+  if (!out) return fail(QS_EINVAL, "qs_expect_pauli: out is NULL");
+  int rc = check_terms("qs_expect_pauli", nterms, x, z, coeff);
+  if (rc) return rc;
+  qs::PauliTable t;
+  Status st = qs::build_pauli_table(s->impl.n, nterms, x, z, coeff, &t);
+  if (!st.good()) return done(st);
+  return done(qs::launch_expect(&s->impl, t, out));
+}
+
+int qs_apply_pauli_sum(qs_state* src, qs_state* dst, int nterms, const uint64_t* x,
+                       const uint64_t* z, const double* coeff) {
+  if (!valid_state(src) || !valid_state(dst)) return fail(QS_EINVAL, "qs_apply_pauli_sum: bad state");
+  if (src->impl.n != dst->impl.n || src->impl.dtype != dst->impl.dtype)
+    return fail(QS_EINVAL, "qs_apply_pauli_sum: states differ in n or dtype");
+  if (src->impl.ptr == dst->impl.ptr) return fail(QS_EINVAL, "qs_apply_pauli_sum: src and dst alias");
+  int rc = check_terms("qs_apply_pauli_sum", nterms, x, z, coeff);
+  if (rc) return rc;
+  qs::PauliTable t;
+  Status st = qs::build_pauli_table(src->impl.n, nterms, x, z, coeff, &t);
+  if (!st.good()) return done(st);
+  return done(qs::launch_apply_pauli_sum(&src->impl, &dst->impl, t));
+}
+
+int qs_grad_adjoint(qs_state* s, const qs_op* ops, int nops, const double* theta, int nparams,
+                    int nterms, const uint64_t* x, const uint64_t* z, const double* coeff,
+                    qs_state* lambda, int flags, double* energy, double* grad) {
+  if (!valid_state(s) || !valid_state(lambda)) return fail(QS_EINVAL, "qs_grad_adjoint: bad state");
+  if (s->impl.n != lambda->impl.n || s->impl.dtype != lambda->impl.dtype)
+    return fail(QS_EINVAL, "qs_grad_adjoint: lambda differs in n or dtype");
+  if (s->impl.ptr == lambda->impl.ptr) return fail(QS_EINVAL, "qs_grad_adjoint: lambda aliases the state");
+  if (nops < 0 || (nops > 0 && !ops)) return fail(QS_EINVAL, "qs_grad_adjoint: bad op list");
+  if (nparams < 0 || (nparams > 0 && !grad)) return fail(QS_EINVAL, "qs_grad_adjoint: bad gradient buffer");
+  if (flags & ~QS_ADJ_STATE_IS_FINAL) return fail(QS_EINVAL, "qs_grad_adjoint: unknown flags");
+  int rc = check_terms("qs_grad_adjoint", nterms, x, z, coeff);
+  if (rc) return rc;
+  std::vector<qs::XGate> gates;
+  Status st = qs::normalize_ops(s->impl.n, ops, nops, theta, nparams, &gates);
+  if (!st.good()) return done(st);
+  qs::PauliTable t;
+  st = qs::build_pauli_table(s->impl.n, nterms, x, z, coeff, &t);
+  if (!st.good()) return done(st);
+  return done(qs::run_adjoint(&s->impl, &lambda->impl, gates, nparams, t, flags, energy, grad));
+}
+
+}  // extern "C"

@@ -1,0 +1,123 @@
+// qs_device.h -- device-side helpers shared by the libqs kernels (gfx950).
+//
+// Amplitudes are interleaved (re, im): double2 for complex128, float2 for
+// complex64; two complex64 amplitudes are moved as one float4 so that every
+// lane issues 16-byte global accesses.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qs {
+
+constexpr int kBlock = 256;  // threads per workgroup of the streaming kernels (4 wave64)
+
+// A 2x2 complex matrix in compute precision R: q11, q12, q21, q22.
+template <typename R>
+struct Mat {
+  R r[4];
+  R i[4];
+};
+
+// out = Q (x, y): one application of Eq. (2) to the amplitude pair (x, y).
+template <typename R>
+__device__ __forceinline__ void mat_apply(const Mat<R>& q, R& xr, R& xi, R& yr, R& yi) {
+  const R ar = q.r[0] * xr - q.i[0] * xi + q.r[1] * yr - q.i[1] * yi;
+  const R ai = q.r[0] * xi + q.i[0] * xr + q.r[1] * yi + q.i[1] * yr;
+  const R br = q.r[2] * xr - q.i[2] * xi + q.r[3] * yr - q.i[3] * yi;
+  const R bi = q.r[2] * xi + q.i[2] * xr + q.r[3] * yi + q.i[3] * yr;
+  xr = ar;
+  xi = ai;
+  yr = br;
+  yi = bi;
+}
+
+// Native vector types used for 16-byte (and 8-byte) global/LDS accesses.
+typedef double d2 __attribute__((ext_vector_type(2)));   // one complex128 amplitude
+typedef float f2 __attribute__((ext_vector_type(2)));    // one complex64 amplitude
+typedef float f4 __attribute__((ext_vector_type(4)));    // two complex64 amplitudes
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void pair_apply(const Mat<double>& q, d2& x, d2& y) {
+  double xr = x.x, xi = x.y, yr = y.x, yi = y.y;
+  mat_apply(q, xr, xi, yr, yi);
+  x = d2{xr, xi};
+  y = d2{yr, yi};
+}
+__device__ __forceinline__ void pair_apply(const Mat<float>& q, f2& x, f2& y) {
+  float xr = x.x, xi = x.y, yr = y.x, yi = y.y;
+  mat_apply(q, xr, xi, yr, yi);
+  x = f2{xr, xi};
+  y = f2{yr, yi};
+}
+// Two complex64 pairs side by side: (x.xy, y.xy) and (x.zw, y.zw).
+__device__ __forceinline__ void pair_apply(const Mat<float>& q, f4& x, f4& y) {
+  float ar = x.x, ai = x.y, br = y.x, bi = y.y;
+  float cr = x.z, ci = x.w, dr = y.z, di = y.w;
+  mat_apply(q, ar, ai, br, bi);
+  mat_apply(q, cr, ci, dr, di);
+  x = f4{ar, ai, cr, ci};
+  y = f4{br, bi, dr, di};
+}
+// A complex64 pair held in one vector: (v.xy, v.zw).
+__device__ __forceinline__ void pair_apply_inner(const Mat<float>& q, f4& v) {
+  float ar = v.x, ai = v.y, br = v.z, bi = v.w;
+  mat_apply(q, ar, ai, br, bi);
+  v = f4{ar, ai, br, bi};
+}
+
+// An amplitude of the storage type from double-precision parts.
+template <typename T>
+__device__ __forceinline__ T make_amp(double re, double im);
+template <>
+__device__ __forceinline__ d2 make_amp<d2>(double re, double im) { return d2{re, im}; }
+template <>
+__device__ __forceinline__ f2 make_amp<f2>(double re, double im) {
+  return f2{(float)re, (float)im};
+}
+
+// Global loads/stores, optionally marked non-temporal (streamed through the
+// caches without being kept: the state is far larger than L2 + MALL).
+template <bool NT, typename T>
+__device__ __forceinline__ T gload(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void gstore(T* p, T v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+// Index p with a 0 bit inserted at position k (bits >= k move up by one).
+__device__ __forceinline__ uint64_t insert0(uint64_t p, int k) {
+  const uint64_t lo = p & ((1ull << k) - 1ull);
+  return ((p ^ lo) << 1) | lo;
+}
+
+// Deterministic wavefront (64-lane) sum by butterfly exchange; every lane
+// ends with the same value, added in the same order on every run.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Deterministic workgroup sum for kBlock threads; `lds` needs kBlock/64
+// doubles.  Every thread receives the result.  Contains barriers: call from
+// uniform control flow only.
+__device__ __forceinline__ double block_sum(double v, double* lds) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) lds[w] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int j = 0; j < kBlock / 64; ++j) s += lds[j];
+  return s;
+}
+
+__device__ __forceinline__ int parity64(uint64_t v) { return __popcll(v) & 1; }
+
+}  // namespace qs

@@ -1,0 +1,316 @@
+"""Python binding of libqs, the MI355X state-vector simulator.
+
+Thin ctypes marshalling over the C ABI declared in include/qs.h: the
+module-level functions carry the C names (qs_create, qs_apply_1q, ...) and
+only convert arguments; every step of the computation runs in the HIP
+kernels of libqs.so.  PyTorch supplies device memory (tensors) and the
+stream (torch.cuda.current_stream()).
+
+The library must be built (python -m paper_1601_07195_amd.build); importing
+this module without libqs.so raises ImportError -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # loaded first: libqs binds to the HIP runtime torch already loaded
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqs.so")
+
+QS_OK, QS_EINVAL, QS_ENOMEM, QS_EHIP, QS_ENODEV, QS_ERANGE = 0, -1, -2, -3, -4, -5
+QS_C64, QS_C128 = 1, 2
+QS_MAX_QUBITS_C128, QS_MAX_QUBITS_C64 = 33, 34
+QS_OP_U, QS_OP_CU, QS_OP_RX, QS_OP_RY, QS_OP_RZ = 0, 1, 2, 3, 4
+QS_RUN_NO_FUSION = 1
+QS_ADJ_STATE_IS_FINAL = 1
+
+# Mirror of `struct qs_op` (80 bytes).
+QS_OP_DTYPE = np.dtype([("kind", "<i4"), ("target", "<i4"), ("control", "<i4"),
+                        ("param", "<i4"), ("mat", "<f8", (8,))])
+
+EXPORTED = ("qs_version", "qs_strerror", "qs_last_error", "qs_create", "qs_destroy",
+            "qs_set_stream", "qs_init_basis", "qs_apply_1q", "qs_apply_cu", "qs_run",
+            "qs_probabilities", "qs_expect_pauli", "qs_apply_pauli_sum", "qs_grad_adjoint")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1601_07195_amd.build`")
+
+_L = ctypes.CDLL(LIB_PATH)
+_vp, _i, _sz, _u64, _dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_uint64, ctypes.c_void_p
+
+_L.qs_version.restype = _i
+_L.qs_strerror.argtypes = [_i]
+_L.qs_strerror.restype = ctypes.c_char_p
+_L.qs_last_error.restype = ctypes.c_char_p
+_L.qs_create.argtypes = [_i, _i, _vp, _sz, _vp, ctypes.POINTER(_vp)]
+_L.qs_destroy.argtypes = [_vp]
+_L.qs_set_stream.argtypes = [_vp, _vp]
+_L.qs_init_basis.argtypes = [_vp, _u64]
+_L.qs_apply_1q.argtypes = [_vp, _i, _dp]
+_L.qs_apply_cu.argtypes = [_vp, _i, _i, _dp]
+_L.qs_run.argtypes = [_vp, _vp, _i, _dp, _i, _i]
+_L.qs_probabilities.argtypes = [_vp, _dp, _dp, _vp, _sz]
+_L.qs_expect_pauli.argtypes = [_vp, _i, _vp, _vp, _dp, _dp]
+_L.qs_apply_pauli_sum.argtypes = [_vp, _vp, _i, _vp, _vp, _dp]
+_L.qs_grad_adjoint.argtypes = [_vp, _vp, _i, _dp, _i, _i, _vp, _vp, _dp, _vp, _i, _dp, _dp]
+for _name in EXPORTED:
+    if _name not in ("qs_strerror", "qs_last_error"):
+        getattr(_L, _name).restype = _i
+
+
+class QSError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = _L.qs_last_error().decode() or _L.qs_strerror(code).decode()
+        super().__init__(f"{where}: {_L.qs_strerror(code).decode()} ({code}): {msg}")
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != QS_OK:
+        raise QSError(rc, where)
+
+
+def lib() -> ctypes.CDLL:
+    return _L
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _mat8(q) -> np.ndarray:
+    q = np.asarray(q)
+    if np.iscomplexobj(q) or q.shape == (2, 2):
+        q = np.asarray(q, dtype=np.complex128).reshape(2, 2)
+        q = np.stack([q.real, q.imag], axis=-1).reshape(8)
+    q = _f64(q)
+    if q.shape != (8,):
+        raise ValueError("a gate is a 2x2 complex matrix or 8 doubles")
+    return q
+
+
+def _ptr(a: np.ndarray | None):
+    return None if a is None else a.ctypes.data
+
+
+def _stream_handle(stream=None) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def ops_array(ops) -> np.ndarray:
+    """Gate records as a contiguous qs_op array (any 80-byte structured
+    array with the same fields is accepted)."""
+    a = np.ascontiguousarray(ops)
+    if a.dtype.itemsize != QS_OP_DTYPE.itemsize or a.dtype.names != QS_OP_DTYPE.names:
+        raise ValueError("ops must be qs_op records")
+    return a.view(QS_OP_DTYPE)
+
+
+def pauli_masks(codes: np.ndarray):
+    """Pauli strings (nterms, n) with codes 0 = I, 1 = X, 2 = Y, 3 = Z ->
+    (x, z) uint64 bit masks as the C ABI takes them."""
+    codes = np.asarray(codes, dtype=np.uint8)
+    if codes.ndim != 2:
+        raise ValueError("codes must be (nterms, n)")
+    n = codes.shape[1]
+    w = (np.uint64(1) << np.arange(n, dtype=np.uint64))
+    x = (((codes == 1) | (codes == 2)).astype(np.uint64) * w).sum(axis=1, dtype=np.uint64)
+    z = (((codes == 3) | (codes == 2)).astype(np.uint64) * w).sum(axis=1, dtype=np.uint64)
+    return np.ascontiguousarray(x, dtype=np.uint64), np.ascontiguousarray(z, dtype=np.uint64)
+
+
+# ------------------------------------------------------ C-named functions
+
+def qs_version() -> int:
+    return _L.qs_version()
+
+
+def qs_strerror(code: int) -> str:
+    return _L.qs_strerror(code).decode()
+
+
+def qs_last_error() -> str:
+    return _L.qs_last_error().decode()
+
+
+def qs_create(n: int, dtype: int, dev_ptr: int, nbytes: int, stream: int | None) -> int:
+    h = _vp()
+    _check(_L.qs_create(n, dtype, dev_ptr, nbytes, stream, ctypes.byref(h)), "qs_create")
+    return h.value
+
+
+def qs_destroy(h: int) -> None:
+    _check(_L.qs_destroy(h), "qs_destroy")
+
+
+def qs_set_stream(h: int, stream: int | None) -> None:
+    _check(_L.qs_set_stream(h, stream), "qs_set_stream")
+
+
+def qs_init_basis(h: int, index: int = 0) -> None:
+    _check(_L.qs_init_basis(h, index), "qs_init_basis")
+
+
+def qs_apply_1q(h: int, k: int, q) -> None:
+    m = _mat8(q)
+    _check(_L.qs_apply_1q(h, k, _ptr(m)), "qs_apply_1q")
+
+
+def qs_apply_cu(h: int, c: int, t: int, q) -> None:
+    m = _mat8(q)
+    _check(_L.qs_apply_cu(h, c, t, _ptr(m)), "qs_apply_cu")
+
+
+def qs_run(h: int, ops, theta=None, flags: int = 0) -> None:
+    a = ops_array(ops)
+    th = _f64(theta) if theta is not None else None
+    _check(_L.qs_run(h, _ptr(a), len(a), _ptr(th), 0 if th is None else len(th), flags), "qs_run")
+
+
+def qs_probabilities(h: int, n: int, full_tensor: torch.Tensor | None = None, want_p1: bool = True):
+    p1 = np.zeros(n, dtype=np.float64) if want_p1 else None
+    nrm = np.zeros(1, dtype=np.float64)
+    fptr, fbytes = None, 0
+    if full_tensor is not None:
+        if full_tensor.dtype != torch.float64 or not full_tensor.is_contiguous():
+            raise ValueError("full probabilities go to a contiguous float64 device tensor")
+        fptr, fbytes = full_tensor.data_ptr(), full_tensor.numel() * 8
+    _check(_L.qs_probabilities(h, _ptr(p1), _ptr(nrm), fptr, fbytes), "qs_probabilities")
+    return p1, float(nrm[0])
+
+
+def qs_expect_pauli(h: int, x, z, coeff) -> float:
+    x = np.ascontiguousarray(x, dtype=np.uint64)
+    z = np.ascontiguousarray(z, dtype=np.uint64)
+    c = _f64(coeff)
+    out = np.zeros(1, dtype=np.float64)
+    _check(_L.qs_expect_pauli(h, len(c), _ptr(x), _ptr(z), _ptr(c), _ptr(out)), "qs_expect_pauli")
+    return float(out[0])
+
+
+def qs_apply_pauli_sum(src: int, dst: int, x, z, coeff) -> None:
+    x = np.ascontiguousarray(x, dtype=np.uint64)
+    z = np.ascontiguousarray(z, dtype=np.uint64)
+    c = _f64(coeff)
+    _check(_L.qs_apply_pauli_sum(src, dst, len(c), _ptr(x), _ptr(z), _ptr(c)), "qs_apply_pauli_sum")
+
+
+def qs_grad_adjoint(h: int, ops, theta, x, z, coeff, lam: int, flags: int = 0):
+    a = ops_array(ops)
+    th = _f64(theta)
+    x = np.ascontiguousarray(x, dtype=np.uint64)
+    z = np.ascontiguousarray(z, dtype=np.uint64)
+    c = _f64(coeff)
+    e = np.zeros(1, dtype=np.float64)
+    g = np.zeros(len(th), dtype=np.float64)
+    _check(_L.qs_grad_adjoint(h, _ptr(a), len(a), _ptr(th), len(th), len(c), _ptr(x), _ptr(z),
+                              _ptr(c), lam, flags, _ptr(e), _ptr(g)), "qs_grad_adjoint")
+    return float(e[0]), g
+
+
+# ------------------------------------------------------------ conveniences
+
+_TORCH_DTYPE = {QS_C128: torch.complex128, QS_C64: torch.complex64}
+
+
+class State:
+    """An n-qubit state in a torch tensor on the current GPU, bound to a
+    libqs handle.  Work is queued on `stream` (default: torch's current
+    stream at construction)."""
+
+    def __init__(self, n: int, dtype: int = QS_C128, device: str | torch.device = "cuda",
+                 stream=None, tensor: torch.Tensor | None = None, init: bool = True):
+        self.n = n
+        self.dtype = dtype
+        if tensor is None:
+            tensor = torch.empty(1 << n, dtype=_TORCH_DTYPE[dtype], device=device)
+        if tensor.dtype != _TORCH_DTYPE[dtype] or not tensor.is_contiguous() or not tensor.is_cuda:
+            raise ValueError("state tensor must be a contiguous GPU tensor of the state dtype")
+        self.tensor = tensor
+        self.stream = stream if stream is not None else torch.cuda.current_stream(tensor.device)
+        self.handle = qs_create(n, dtype, tensor.data_ptr(), tensor.numel() * tensor.element_size(),
+                                self.stream.cuda_stream)
+        if init:
+            qs_init_basis(self.handle, 0)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            qs_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_basis(self, index: int = 0) -> "State":
+        qs_init_basis(self.handle, index)
+        return self
+
+    def apply_1q(self, k: int, q) -> "State":
+        qs_apply_1q(self.handle, k, q)
+        return self
+
+    def apply_cu(self, c: int, t: int, q) -> "State":
+        qs_apply_cu(self.handle, c, t, q)
+        return self
+
+    def run(self, ops, theta=None, fuse: bool = True) -> "State":
+        qs_run(self.handle, ops, theta, 0 if fuse else QS_RUN_NO_FUSION)
+        return self
+
+    def probabilities(self, full: bool = False):
+        ft = torch.empty(1 << self.n, dtype=torch.float64, device=self.tensor.device) if full else None
+        p1, nrm = qs_probabilities(self.handle, self.n, ft)
+        return p1, nrm, ft
+
+    def expect(self, codes, coeff) -> float:
+        x, z = pauli_masks(codes)
+        return qs_expect_pauli(self.handle, x, z, coeff)
+
+    def numpy(self) -> np.ndarray:
+        self.stream.synchronize()
+        return self.tensor.detach().cpu().numpy().astype(np.complex128)
+
+
+def grad_adjoint(state: State, lam: State, ops, theta, codes, coeff, state_is_final: bool = False):
+    """Energy and adjoint gradient; see qs_grad_adjoint."""
+    x, z = pauli_masks(codes)
+    flags = QS_ADJ_STATE_IS_FINAL if state_is_final else 0
+    return qs_grad_adjoint(state.handle, ops, theta, x, z, coeff, lam.handle, flags)
+
+
+class AdjointEnergy(torch.autograd.Function):
+    """E(theta) = <0|U(theta)^dagger H U(theta)|0> with d E / d theta from
+    one adjoint reverse sweep.
+
+    forward(theta, ops, n, codes, coeff, dtype) runs the circuit (qs_run) and
+    the expectation (qs_expect_pauli); backward runs qs_grad_adjoint on the
+    state the forward left behind, so the forward sweep is not repeated.
+    theta is a float64 CPU or GPU tensor; E is returned as a 0-d float64
+    tensor on theta's device."""
+
+    @staticmethod
+    def forward(ctx, theta, ops, n, codes, coeff, dtype=QS_C128):
+        th = theta.detach().to("cpu", torch.float64).numpy()
+        st = State(n, dtype)
+        st.run(ops, th)
+        x, z = pauli_masks(codes)
+        e = qs_expect_pauli(st.handle, x, z, coeff)
+        ctx.saved = (st, ops, th, codes, coeff, dtype, n)
+        return torch.tensor(e, dtype=torch.float64, device=theta.device)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        st, ops, th, codes, coeff, dtype, n = ctx.saved
+        lam = State(n, dtype, init=False)
+        _, g = grad_adjoint(st, lam, ops, th, codes, coeff, state_is_final=True)
+        ctx.saved = None
+        gt = torch.from_numpy(g).to(grad_out.device) * grad_out
+        return gt, None, None, None, None, None

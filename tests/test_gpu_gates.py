@@ -1,0 +1,169 @@
+"""GPU parity of the gate kernels (Eq. 2, Eq. 3) and state init against the
+CPU oracle, element by element, through the C ABI.
+
+Tolerance: complex128 max |amplitude error| <= 1e-12.  complex64 results are
+compared with the oracle applied to the same (complex64-rounded) input; their
+error is reported and bounded only loosely (1e-6), complex64 precision being
+the point of that dtype."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import circuits as C
+import oracle as O
+from tests.gpu_util import Q, random_state, rounded_input, to_gpu_state  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+TOL128 = 1e-12
+TOL64 = 1e-6
+DTYPES = ["c128", "c64"]
+
+
+def dt(Q, name):
+    return Q.QS_C128 if name == "c128" else Q.QS_C64
+
+
+def tol(name):
+    return TOL128 if name == "c128" else TOL64
+
+
+@pytest.mark.parametrize("name", DTYPES)
+@pytest.mark.parametrize("n", [1, 2, 5, 13])
+def test_init_basis_exact(Q, name, n):
+    rng = np.random.default_rng(n)
+    for index in {0, (1 << n) - 1, int(rng.integers(1 << n))}:
+        st = Q.State(n, dt(Q, name), init=False)
+        st.init_basis(index)
+        got = st.numpy()
+        ref = O.basis_state(n, index)
+        assert np.array_equal(got, ref), index
+
+
+@pytest.mark.parametrize("name", DTYPES)
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 11, 14])
+def test_1q_every_target(Q, name, n):
+    rng = np.random.default_rng(100 + n)
+    psi = random_state(n, rng)
+    st = to_gpu_state(Q, psi, dt(Q, name))
+    ref = rounded_input(psi, name == "c64")
+    for k in range(n):
+        u = C.haar_unitary(rng)
+        st.apply_1q(k, u)
+        O.apply_1q(ref, n, k, u)
+        got = st.numpy()
+        err = np.abs(got - ref).max()
+        assert err <= tol(name), (k, err)
+        ref = rounded_input(got, name == "c64") if name == "c64" else ref
+
+
+@pytest.mark.parametrize("name", DTYPES)
+@pytest.mark.parametrize("n", [2, 3, 5, 9])
+def test_cu_every_pair(Q, name, n):
+    rng = np.random.default_rng(200 + n)
+    psi = random_state(n, rng)
+    st = to_gpu_state(Q, psi, dt(Q, name))
+    ref = rounded_input(psi, name == "c64")
+    for c in range(n):
+        for t in range(n):
+            if c == t:
+                continue
+            u = C.haar_unitary(rng)
+            st.apply_cu(c, t, u)
+            O.apply_cu(ref, n, c, t, u)
+            got = st.numpy()
+            err = np.abs(got - ref).max()
+            assert err <= tol(name), (c, t, err)
+            if name == "c64":
+                ref = rounded_input(got, True)
+
+
+@pytest.mark.parametrize("name", DTYPES)
+def test_cu_sampled_pairs_ragged_sizes(Q, name):
+    rng = np.random.default_rng(300)
+    for n in (12, 15):
+        psi = random_state(n, rng)
+        st = to_gpu_state(Q, psi, dt(Q, name))
+        ref = rounded_input(psi, name == "c64")
+        pairs = [(0, n - 1), (n - 1, 0), (1, 2), (2, 1), (0, 1), (1, 0)] + \
+            [tuple(int(v) for v in rng.choice(n, 2, replace=False)) for _ in range(6)]
+        for c, t in pairs:
+            u = C.haar_unitary(rng)
+            st.apply_cu(c, t, u)
+            O.apply_cu(ref, n, c, t, u)
+            got = st.numpy()
+            assert np.abs(got - ref).max() <= tol(name), (n, c, t)
+            if name == "c64":
+                ref = rounded_input(got, True)
+
+
+def test_cnot_exact_permutation_on_gpu(Q):
+    n = 12
+    psi = random_state(n, np.random.default_rng(7))
+    idx = np.arange(1 << n)
+    for c, t in [(0, 1), (5, 0), (11, 3), (3, 11)]:
+        st = to_gpu_state(Q, psi, Q.QS_C128)
+        st.apply_cu(c, t, C.X_GATE)
+        perm = np.where((idx >> c) & 1, idx ^ (1 << t), idx)
+        assert np.array_equal(st.numpy(), psi[perm])
+
+
+def test_random_circuit_workload_n20(Q):
+    """200-gate random 1q / controlled-U mix from |0...0> at n = 20: full
+    state and per-qubit probabilities."""
+    circ = C.workload_gates(20, 200)
+    ref = O.run(circ.ops, 20)
+    st = Q.State(20, Q.QS_C128)
+    st.run(circ.ops, fuse=False)
+    got = st.numpy()
+    assert np.abs(got - ref).max() <= TOL128
+    p1, nrm, _ = st.probabilities()
+    rp1, rnrm, _ = O.probabilities(ref, 20)
+    assert np.abs(p1 - rp1).max() <= TOL128
+    assert abs(nrm - rnrm) <= TOL128
+
+
+def _bitrev(z, n):
+    return int(format(z, "0%db" % n)[::-1], 2)
+
+
+def test_qft_basis_state_closed_form_gpu(Q):
+    n = 12
+    x = 0b101100111010
+    st = Q.State(n, Q.QS_C128, init=False).init_basis(x)
+    st.run(C.qft_circuit(n).ops, fuse=False)
+    got = st.numpy()
+    N = 1 << n
+    rev = np.array([_bitrev(z, n) for z in range(N)])
+    ref = np.exp(2j * np.pi * ((x * rev) % N) / N) / math.sqrt(N)
+    assert np.abs(got - ref).max() <= TOL128
+
+
+def test_u_then_udagger_on_gpu(Q):
+    n = 16
+    circ = C.random_circuit(n, 100, np.random.default_rng(9))
+    inv = circ.ops[::-1].copy()
+    for op in inv:
+        op["mat"] = C.mat_to_row(C.row_to_mat(op["mat"]).conj().T)
+    psi = random_state(n, np.random.default_rng(10))
+    st = to_gpu_state(Q, psi, Q.QS_C128)
+    st.run(circ.ops, fuse=False).run(inv, fuse=False)
+    assert np.abs(st.numpy() - psi).max() <= TOL128
+
+
+def test_argument_errors_queue_nothing(Q):
+    n = 6
+    psi = random_state(n, np.random.default_rng(11))
+    st = to_gpu_state(Q, psi, Q.QS_C128)
+    with pytest.raises(Q.QSError):
+        st.apply_1q(n, C.H_GATE)
+    with pytest.raises(Q.QSError):
+        st.apply_cu(2, 2, C.X_GATE)
+    bad = C.workload_gates(n, 5).ops.copy()
+    bad[3]["target"] = 17
+    with pytest.raises(Q.QSError):
+        st.run(bad)
+    assert np.array_equal(st.numpy(), psi)
