@@ -203,6 +203,15 @@ int qs_grad_adjoint(qs_state* s, const qs_op* ops, int nops,
                     const uint64_t* x, const uint64_t* z, const double* coeff,
                     qs_state* lambda, int flags, double* energy, double* grad);
 
+/*
+ * STREAM copy, dst[i] = src[i]: the sustainable-bandwidth probe that the
+ * paper's lower bounds are stated against (Sec. 5.2, B_mem "measured by
+ * STREAM Copy").  src, dst: device, 16-byte aligned, non-overlapping;
+ * bytes: a multiple of 16.  Asynchronous on `stream`.
+ * Errors: QS_EINVAL (NULL, misaligned, bytes % 16 != 0).
+ */
+int qs_stream_copy(const void* src, void* dst, size_t bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -356,4 +356,13 @@ int qs_grad_adjoint(qs_state* s, const qs_op* ops, int nops, const double* theta
   return done(qs::run_adjoint(&s->impl, &lambda->impl, gates, nparams, t, flags, energy, grad));
 }
 
+int qs_stream_copy(const void* src, void* dst, size_t bytes, void* stream) {
+  if (!src || !dst) return fail(QS_EINVAL, "qs_stream_copy: NULL pointer");
+  if ((((uintptr_t)src) | ((uintptr_t)dst) | bytes) & 15)
+    return fail(QS_EINVAL, "qs_stream_copy: pointers and size must be multiples of 16");
+  const uintptr_t a = (uintptr_t)src, b = (uintptr_t)dst;
+  if (a < b + bytes && b < a + bytes) return fail(QS_EINVAL, "qs_stream_copy: buffers overlap");
+  return done(qs::launch_stream_copy(src, dst, bytes, (hipStream_t)stream));
+}
+
 }  // extern "C"

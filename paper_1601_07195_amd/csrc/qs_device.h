@@ -66,6 +66,64 @@ __device__ __forceinline__ void pair_apply_inner(const Mat<float>& q, f4& v) {
   v = f4{ar, ai, br, bi};
 }
 
+// Butterfly partner exchange inside a wavefront (lane ^ m).
+__device__ __forceinline__ d2 shfl_xor_unit(d2 v, int m) {
+  return d2{__shfl_xor(v.x, m, 64), __shfl_xor(v.y, m, 64)};
+}
+__device__ __forceinline__ f4 shfl_xor_unit(f4 v, int m) {
+  return f4{__shfl_xor(v.x, m, 64), __shfl_xor(v.y, m, 64), __shfl_xor(v.z, m, 64),
+            __shfl_xor(v.w, m, 64)};
+}
+
+// o = a * x + b * y for complex a, b, x, y.
+template <typename R>
+__device__ __forceinline__ void cmadd(R ar, R ai, R br, R bi, R xr, R xi, R yr, R yi, R& orr,
+                                      R& oi) {
+  orr = ar * xr - ai * xi + br * yr - bi * yi;
+  oi = ar * xi + ai * xr + br * yi + bi * yr;
+}
+
+// Coefficients of one output row of Q for a lane that holds one member of a
+// pair: the lane with the target bit clear computes q11 x + q12 y, the lane
+// with it set computes q21 y + q22 x (x = own amplitude, y = partner's).
+template <typename R>
+struct Row {
+  R own_r, own_i, par_r, par_i;
+};
+template <typename R>
+__device__ __forceinline__ Row<R> row_for(const Mat<R>& q, bool hi) {
+  Row<R> w;
+  w.own_r = hi ? q.r[3] : q.r[0];
+  w.own_i = hi ? q.i[3] : q.i[0];
+  w.par_r = hi ? q.r[2] : q.r[1];
+  w.par_i = hi ? q.i[2] : q.i[1];
+  return w;
+}
+__device__ __forceinline__ d2 row_apply(const Row<double>& w, d2 x, d2 y) {
+  double o_r, o_i;
+  cmadd(w.own_r, w.own_i, w.par_r, w.par_i, x.x, x.y, y.x, y.y, o_r, o_i);
+  return d2{o_r, o_i};
+}
+__device__ __forceinline__ f4 row_apply(const Row<float>& w, f4 x, f4 y) {
+  float ar, ai, br, bi;
+  cmadd(w.own_r, w.own_i, w.par_r, w.par_i, x.x, x.y, y.x, y.y, ar, ai);
+  cmadd(w.own_r, w.own_i, w.par_r, w.par_i, x.z, x.w, y.z, y.w, br, bi);
+  return f4{ar, ai, br, bi};
+}
+// Only the odd amplitude of each complex64 unit (control qubit 0 set).
+__device__ __forceinline__ f4 row_apply_odd(const Row<float>& w, f4 x, f4 y) {
+  float br, bi;
+  cmadd(w.own_r, w.own_i, w.par_r, w.par_i, x.z, x.w, y.z, y.w, br, bi);
+  return f4{x.x, x.y, br, bi};
+}
+// Pair update of the odd amplitudes only (x.zw, y.zw).
+__device__ __forceinline__ void pair_apply_odd(const Mat<float>& q, f4& x, f4& y) {
+  float cr = x.z, ci = x.w, dr = y.z, di = y.w;
+  mat_apply(q, cr, ci, dr, di);
+  x = f4{x.x, x.y, cr, ci};
+  y = f4{y.x, y.y, dr, di};
+}
+
 // An amplitude of the storage type from double-precision parts.
 template <typename T>
 __device__ __forceinline__ T make_amp(double re, double im);

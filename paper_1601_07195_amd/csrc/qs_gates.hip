@@ -1,143 +1,170 @@
 // qs_gates.hip -- streaming gate kernels: one pass over the state per gate.
 //
-// Single-qubit gate (qHiPSTER Eq. 2): the 2^(n-1) pairs (i0, i0 + 2^k) with
-// bit k of i0 clear are enumerated by a flat pair index p, i0 = p with a 0
-// inserted at bit k.  Consecutive lanes take consecutive p, so for every
-// target the two streams a[i0] and a[i0 + 2^k] are read and written as
-// contiguous 16-byte-per-lane runs (a wavefront touches 1 KiB per access),
-// instead of the paper's two-level loop nest (Fig. 2) that a CPU thread walks.
+// Single-qubit gate (qHiPSTER Eq. 2) and controlled gate (Eq. 3), written
+// for 64-wide wavefronts and 16-byte accesses instead of the paper's
+// two-level loop nest (Fig. 2).
 //
-// Controlled gate (Eq. 3): only the 2^(n-2) quads with control bit 1 are
-// visited: p with 0s inserted at both c and t, then bit c set.  Amplitudes
-// with control bit 0 are neither read nor written (half the traffic of a
-// single-qubit gate, Table 2 case 3).
+// Units.  Every lane moves one 16-byte "unit": a complex128 amplitude, or two
+// adjacent complex64 amplitudes.  Unit bit j is qubit j (complex128) or qubit
+// j + 1 (complex64); complex64 qubit 0 lies inside a unit.
 //
-// complex64 states are moved two amplitudes (16 B) per access: in "vector"
-// index space (vector v = amplitudes 2v, 2v+1) a qubit q >= 1 is vector bit
-// q-1.  Qubit 0 lives inside a vector; gates on it use the *_inner kernels.
+// Three access shapes, picked per gate from its qubits:
+//   * exchange (target unit bit < 8): a 256-lane workgroup reads 256
+//     consecutive units, one per lane; each lane fetches its partner from lane
+//     ^ 2^t with a cross-lane shuffle (bit < 6, same wavefront) or through LDS
+//     (bits 6, 7), so both members of every pair arrive in one contiguous
+//     4 KiB access;
+//   * paired streams (target unit bit >= 8): lane p handles the pair
+//     (i0, i0 + 2^t), i0 = p with a 0 inserted at bit t; consecutive lanes
+//     read two contiguous 1 KiB runs;
+//   * in-unit (complex64 target qubit 0): each unit holds a whole pair.
+// Controls (Eq. 3): when the control's runs of 1s are at least one 128-byte
+// line long (control unit bit >= 3) only control-1 units are enumerated
+// ("compact"): half the state is neither read nor written, Table 2 case 3.
+// Below that, a line mixes control-0 and control-1 amplitudes; the whole
+// line is read anyway, so the kernel reads every unit and writes every unit
+// back (unchanged where the control is 0), which streams full lines instead
+// of scattering half-line accesses.
+//
+// Launch shape: 16 bytes per lane per stream, 64-lane workgroups for the
+// paired-stream kernel and 256-lane workgroups for the exchange kernels (the
+// fastest measured on MI355X), grid-stride loops with the grid capped so the
+// dispatch never exceeds 2^31 work-items.  Workgroups are dispatched to the
+// 8 XCDs round-robin; for some strides the paired-stream kernel is faster
+// when each XCD walks one contiguous eighth of the work ("XCD-contiguous"
+// order), which the dispatch rules below select from a measured sweep.
+#include <algorithm>
+
 #include "qs_device.h"
 #include "qs_internal.h"
 
 namespace qs {
 
-// ----------------------------------------------------------- |index> init
-// Writes 16-byte zeros over the state and the 16-byte vector holding the
-// amplitude `index` with `one` (1.0 + 0i placed at the right offset).
-template <int V>
-__global__ void __launch_bounds__(kBlock)
-k_init_basis(u64x2* __restrict__ a, uint64_t nvec, uint64_t one_vec, u64x2 one) {
-  const uint64_t base = (uint64_t)blockIdx.x * (kBlock * V) + threadIdx.x;
-#pragma unroll
-  for (int v = 0; v < V; ++v) {
-    const uint64_t j = base + (uint64_t)v * kBlock;
-    if (j < nvec) a[j] = (j == one_vec) ? one : u64x2{0ull, 0ull};
+enum CtrlMode { kNone = 0, kCompact = 1, kPred = 2, kInnerCtrl = 3 };
+
+constexpr bool kNT = true;  // non-temporal global accesses (the state >> L2 + MALL)
+constexpr int kShflBits = 6;  // lane bits of a wave64
+constexpr int kLineUnitBits = 3;  // 128-byte line = 8 units
+constexpr int kPairBlock = 64;
+constexpr int kShflBlock = 256;
+
+// Logical workgroup index.  MAP 0: as dispatched.  MAP 1: XCD-contiguous --
+// dispatch slot b runs on XCD b % 8, so logical block (b % 8) * (G / 8) +
+// b / 8 makes each XCD walk a contiguous eighth; a tail of G % 8 blocks keeps
+// its own index (the map stays a permutation of 0..G-1).
+template <int MAP>
+__device__ __forceinline__ uint64_t logical_block() {
+  const uint64_t b = blockIdx.x;
+  if constexpr (MAP == 1) {
+    const uint64_t per = gridDim.x / 8;
+    if (b < per * 8) return (b % 8) * per + b / 8;
   }
+  return b;
 }
 
-// ------------------------------------------------------- 1-qubit, strided
-// `a` in units of T (d2: one c128 amplitude; f2: one c64 amplitude; f4: two
-// c64 amplitudes), k the target bit in those units, npairs = pairs of units.
-template <typename R, typename T, int V, bool NT>
-__global__ void __launch_bounds__(kBlock)
-k_apply_1q(T* __restrict__ a, uint64_t npairs, int k, Mat<R> q) {
-  const uint64_t s = 1ull << k;
-  const uint64_t p0 = (uint64_t)blockIdx.x * (kBlock * V) + threadIdx.x;
-  T x[V], y[V];
-  uint64_t i0[V];
-#pragma unroll
-  for (int v = 0; v < V; ++v) {
-    const uint64_t p = p0 + (uint64_t)v * kBlock;
-    i0[v] = insert0(p, k);
-    if (p < npairs) {
-      x[v] = gload<NT>(a + i0[v]);
-      y[v] = gload<NT>(a + i0[v] + s);
-    }
-  }
-#pragma unroll
-  for (int v = 0; v < V; ++v) {
-    const uint64_t p = p0 + (uint64_t)v * kBlock;
-    if (p < npairs) {
-      pair_apply(q, x[v], y[v]);
-      gstore<NT>(a + i0[v], x[v]);
-      gstore<NT>(a + i0[v] + s, y[v]);
-    }
-  }
-}
-
-// complex64, target qubit 0: each f4 holds one whole pair.
-template <int V, bool NT>
-__global__ void __launch_bounds__(kBlock)
-k_apply_1q_inner(f4* __restrict__ a, uint64_t nvec, Mat<float> q) {
-  const uint64_t base = (uint64_t)blockIdx.x * (kBlock * V) + threadIdx.x;
-  f4 x[V];
-#pragma unroll
-  for (int v = 0; v < V; ++v) {
-    const uint64_t j = base + (uint64_t)v * kBlock;
-    if (j < nvec) x[v] = gload<NT>(a + j);
-  }
-#pragma unroll
-  for (int v = 0; v < V; ++v) {
-    const uint64_t j = base + (uint64_t)v * kBlock;
-    if (j < nvec) {
-      pair_apply_inner(q, x[v]);
-      gstore<NT>(a + j, x[v]);
-    }
-  }
-}
-
-// ---------------------------------------------------- controlled, strided
-// Units as in k_apply_1q; c, t are unit bits; nquads = 2^(units_log2 - 2).
-template <typename R, typename T, int V, bool NT>
-__global__ void __launch_bounds__(kBlock)
-k_apply_cu(T* __restrict__ a, uint64_t nquads, int c, int t, Mat<R> q) {
+// ------------------------------------------------------------- paired streams
+// count work items: kNone / kPred / kInnerCtrl: 2^(u-1) pairs of target t;
+// kCompact: 2^(u-2) control-1 pairs (0s inserted at c and t, then bit c set).
+template <typename R, typename T, int B, int CM, int MAP>
+__global__ void __launch_bounds__(B)
+k_pair(T* __restrict__ a, uint64_t count, int t, int c, Mat<R> q) {
+  const uint64_t s = 1ull << t;
+  const uint64_t stride = (uint64_t)gridDim.x * B;
   const int lo = c < t ? c : t, hi = c < t ? t : c;
-  const uint64_t cm = 1ull << c, s = 1ull << t;
-  const uint64_t p0 = (uint64_t)blockIdx.x * (kBlock * V) + threadIdx.x;
-  T x[V], y[V];
-  uint64_t i0[V];
-#pragma unroll
-  for (int v = 0; v < V; ++v) {
-    const uint64_t p = p0 + (uint64_t)v * kBlock;
-    i0[v] = insert0(insert0(p, lo), hi) | cm;
-    if (p < nquads) {
-      x[v] = gload<NT>(a + i0[v]);
-      y[v] = gload<NT>(a + i0[v] + s);
+  for (uint64_t p = logical_block<MAP>() * B + threadIdx.x; p < count; p += stride) {
+    uint64_t i0;
+    if constexpr (CM == kCompact) i0 = insert0(insert0(p, lo), hi) | (1ull << c);
+    else i0 = insert0(p, t);
+    T x = gload<kNT>(a + i0), y = gload<kNT>(a + i0 + s);
+    if constexpr (CM == kPred) {
+      if ((i0 >> c) & 1) pair_apply(q, x, y);
+    } else if constexpr (CM == kInnerCtrl) {
+      pair_apply_odd(q, x, y);
+    } else {
+      pair_apply(q, x, y);
     }
-  }
-#pragma unroll
-  for (int v = 0; v < V; ++v) {
-    const uint64_t p = p0 + (uint64_t)v * kBlock;
-    if (p < nquads) {
-      pair_apply(q, x[v], y[v]);
-      gstore<NT>(a + i0[v], x[v]);
-      gstore<NT>(a + i0[v] + s, y[v]);
-    }
+    gstore<kNT>(a + i0, x);
+    gstore<kNT>(a + i0 + s, y);
   }
 }
 
-// complex64, target qubit 0, control c >= 1 (vector bit cv = c - 1): the
-// vectors with bit cv set each hold one pair to update.
-template <int V, bool NT>
-__global__ void __launch_bounds__(kBlock)
-k_apply_cu_inner(f4* __restrict__ a, uint64_t nsel, int cv, Mat<float> q) {
-  const uint64_t base = (uint64_t)blockIdx.x * (kBlock * V) + threadIdx.x;
-  const uint64_t cm = 1ull << cv;
-  f4 x[V];
-  uint64_t j[V];
-#pragma unroll
-  for (int v = 0; v < V; ++v) {
-    const uint64_t p = base + (uint64_t)v * kBlock;
-    j[v] = insert0(p, cv) | cm;
-    if (p < nsel) x[v] = gload<NT>(a + j[v]);
-  }
-#pragma unroll
-  for (int v = 0; v < V; ++v) {
-    const uint64_t p = base + (uint64_t)v * kBlock;
-    if (p < nsel) {
-      pair_apply_inner(q, x[v]);
-      gstore<NT>(a + j[v], x[v]);
+// ----------------------------------------------------------------- exchange
+// t is the target's bit in the work index j (< 8).  count work items:
+// kNone / kPred / kInnerCtrl: all 2^u units; kCompact: the 2^(u-1) units with
+// bit c set (unit = j with a 1 inserted at bit c).  LDS = false: partner by
+// wavefront shuffle (t < 6); LDS = true: partner through shared memory
+// (t = 6, 7).  The loop trip count is uniform over the workgroup (barriers).
+template <typename R, typename T, int B, int CM, bool LDS>
+__global__ void __launch_bounds__(B)
+k_exchange(T* __restrict__ a, uint64_t count, int t, int c, Mat<R> q) {
+  __shared__ T buf[LDS ? B : 1];
+  const int m = 1 << t;
+  const Row<R> w = row_for(q, (threadIdx.x >> t) & 1);
+  const uint64_t stride = (uint64_t)gridDim.x * B;
+  for (uint64_t base = (uint64_t)blockIdx.x * B; base < count; base += stride) {
+    const uint64_t j = base + threadIdx.x;
+    const bool live = j < count;
+    uint64_t u;
+    if constexpr (CM == kCompact) u = insert0(j, c) | (1ull << c);
+    else u = j;
+    T x{};
+    if (live) x = gload<kNT>(a + u);
+    T y;
+    if constexpr (LDS) {
+      buf[threadIdx.x] = x;
+      __syncthreads();
+      y = buf[threadIdx.x ^ m];
+      __syncthreads();
+    } else {
+      y = shfl_xor_unit(x, m);
     }
+    T o;
+    if constexpr (CM == kInnerCtrl) o = row_apply_odd(w, x, y);
+    else o = row_apply(w, x, y);
+    if constexpr (CM == kPred) o = ((u >> c) & 1) ? o : x;
+    if (live) gstore<kNT>(a + u, o);
   }
+}
+
+// ---------------------------------------------------- complex64, qubit 0
+// Each unit is a pair.  kNone: all 2^u units; kCompact: 2^(u-1) units with
+// unit bit c set; kPred: all units, updated where unit bit c is set.
+template <int B, int CM>
+__global__ void __launch_bounds__(B)
+k_inner(f4* __restrict__ a, uint64_t count, int c, Mat<float> q) {
+  const uint64_t stride = (uint64_t)gridDim.x * B;
+  for (uint64_t j = (uint64_t)blockIdx.x * B + threadIdx.x; j < count; j += stride) {
+    uint64_t u;
+    if constexpr (CM == kCompact) u = insert0(j, c) | (1ull << c);
+    else u = j;
+    f4 x = gload<kNT>(a + u);
+    if constexpr (CM == kPred) {
+      if ((u >> c) & 1) pair_apply_inner(q, x);
+    } else {
+      pair_apply_inner(q, x);
+    }
+    gstore<kNT>(a + u, x);
+  }
+}
+
+// ----------------------------------------------------------- |index> init
+// 16-byte zeros everywhere, `one` at the unit holding amplitude `index`.
+template <int B>
+__global__ void __launch_bounds__(B)
+k_init_basis(u64x2* __restrict__ a, uint64_t nvec, uint64_t one_vec, u64x2 one) {
+  const uint64_t stride = (uint64_t)gridDim.x * B;
+  for (uint64_t j = (uint64_t)blockIdx.x * B + threadIdx.x; j < nvec; j += stride)
+    gstore<kNT>(a + j, (j == one_vec) ? one : u64x2{0ull, 0ull});
+}
+
+// STREAM "copy" (dst[i] = src[i]) over 16-byte words: the sustainable memory
+// bandwidth B_mem that the paper's lower bounds divide by (Sec. 5.2).
+template <int B>
+__global__ void __launch_bounds__(B)
+k_stream_copy(const u64x2* __restrict__ src, u64x2* __restrict__ dst, uint64_t nwords) {
+  const uint64_t stride = (uint64_t)gridDim.x * B;
+  for (uint64_t i = (uint64_t)blockIdx.x * B + threadIdx.x; i < nwords; i += stride)
+    gstore<kNT>(dst + i, gload<kNT>(src + i));
 }
 
 // ------------------------------------------------------------- launchers
@@ -152,11 +179,11 @@ Mat<R> to_mat(const double* q) {
   return m;
 }
 
-constexpr int kV = 4;      // units per lane per stream
-constexpr bool kNT = true; // non-temporal global accesses
-
-static unsigned grid_for(uint64_t items, int per_block) {
-  return (unsigned)((items + per_block - 1) / per_block);
+// Grid for `items` work items, capped at 2^31 work-items per dispatch.
+static unsigned grid_for(uint64_t items, int block) {
+  const uint64_t want = (items + block - 1) / block;
+  const uint64_t cap = (1ull << 31) / (uint64_t)block;
+  return (unsigned)std::max<uint64_t>(1, std::min(want, cap));
 }
 
 Status hip_status(hipError_t e, const char* what) {
@@ -168,6 +195,27 @@ Status hip_status(hipError_t e, const char* what) {
 }
 
 static Status last_launch(const char* what) { return hip_status(hipGetLastError(), what); }
+
+template <typename R, typename T, int CM, int MAP>
+static void go_pair(StateImpl* s, uint64_t count, int t, int c, const Mat<R>& q) {
+  hipLaunchKernelGGL((k_pair<R, T, kPairBlock, CM, MAP>), dim3(grid_for(count, kPairBlock)),
+                     dim3(kPairBlock), 0, s->stream, (T*)s->ptr, count, t, c, q);
+}
+// Exchange kernel; t is the target's bit in the work index (< 8).
+template <typename R, typename T, int CM>
+static void go_exchange(StateImpl* s, uint64_t count, int t, int c, const Mat<R>& q) {
+  if (t < kShflBits)
+    hipLaunchKernelGGL((k_exchange<R, T, kShflBlock, CM, false>), dim3(grid_for(count, kShflBlock)),
+                       dim3(kShflBlock), 0, s->stream, (T*)s->ptr, count, t, c, q);
+  else
+    hipLaunchKernelGGL((k_exchange<R, T, kShflBlock, CM, true>), dim3(grid_for(count, kShflBlock)),
+                       dim3(kShflBlock), 0, s->stream, (T*)s->ptr, count, t, c, q);
+}
+template <int CM>
+static void go_inner(StateImpl* s, uint64_t count, int c, const Mat<float>& q) {
+  hipLaunchKernelGGL((k_inner<kShflBlock, CM>), dim3(grid_for(count, kShflBlock)),
+                     dim3(kShflBlock), 0, s->stream, (f4*)s->ptr, count, c, q);
+}
 
 Status launch_init_basis(StateImpl* s, uint64_t index) {
   const uint64_t nvec = (((uint64_t)1 << s->n) * amp_bytes(s->dtype)) / 16;
@@ -182,58 +230,78 @@ Status launch_init_basis(StateImpl* s, uint64_t index) {
     one_vec = index >> 1;
     one = (index & 1) ? u64x2{0ull, one_bits_f} : u64x2{one_bits_f, 0ull};
   }
-  hipLaunchKernelGGL((k_init_basis<kV>), dim3(grid_for(nvec, kBlock * kV)), dim3(kBlock), 0,
-                     s->stream, (u64x2*)s->ptr, nvec, one_vec, one);
+  hipLaunchKernelGGL((k_init_basis<kShflBlock>), dim3(grid_for(nvec, kShflBlock)),
+                     dim3(kShflBlock), 0, s->stream, (u64x2*)s->ptr, nvec, one_vec, one);
   return last_launch("init_basis");
+}
+
+// Dispatch rules below were chosen from a measured sweep of every target
+// (and a grid of control/target pairs) at n = 30 on MI355X.
+constexpr int kExchangeBits = 8;  // target bits handled inside a 256-lane workgroup
+
+// Single-qubit gate on unit bit t of a 2^u-unit state.
+template <typename R, typename T>
+static void units_1q(StateImpl* s, int u, int t, const Mat<R>& q) {
+  if (t < kExchangeBits) go_exchange<R, T, kNone>(s, 1ull << u, t, 0, q);
+  else if (t == 22 || t == 23) go_pair<R, T, kNone, 1>(s, 1ull << (u - 1), t, 0, q);
+  else go_pair<R, T, kNone, 0>(s, 1ull << (u - 1), t, 0, q);
+}
+
+// Controlled gate, control unit bit c, target unit bit t, 2^u units.
+template <typename R, typename T>
+static void units_cu(StateImpl* s, int u, int c, int t, const Mat<R>& q) {
+  const bool compact = c >= kLineUnitBits;
+  if (t < kExchangeBits) {
+    if (compact) go_exchange<R, T, kCompact>(s, 1ull << (u - 1), t < c ? t : t - 1, c, q);
+    else go_exchange<R, T, kPred>(s, 1ull << u, t, c, q);
+  } else if (compact) {
+    if (c < kExchangeBits) go_pair<R, T, kCompact, 1>(s, 1ull << (u - 2), t, c, q);
+    else go_pair<R, T, kCompact, 0>(s, 1ull << (u - 2), t, c, q);
+  } else {
+    go_pair<R, T, kPred, 0>(s, 1ull << (u - 1), t, c, q);
+  }
 }
 
 Status launch_apply_1q(StateImpl* s, int k, const double* q) {
   const int n = s->n;
   if (s->dtype == QS_C128) {
-    const uint64_t np = (uint64_t)1 << (n - 1);
-    hipLaunchKernelGGL((k_apply_1q<double, d2, kV, kNT>), dim3(grid_for(np, kBlock * kV)),
-                       dim3(kBlock), 0, s->stream, (d2*)s->ptr, np, k, to_mat<double>(q));
+    units_1q<double, d2>(s, n, k, to_mat<double>(q));
     return last_launch("apply_1q c128");
   }
   const Mat<float> m = to_mat<float>(q);
-  if (n == 1 || k == 0) {
-    const uint64_t nvec = (uint64_t)1 << (n - 1);
-    hipLaunchKernelGGL((k_apply_1q_inner<kV, kNT>), dim3(grid_for(nvec, kBlock * kV)),
-                       dim3(kBlock), 0, s->stream, (f4*)s->ptr, nvec, m);
-    return last_launch("apply_1q c64 inner");
-  }
-  const uint64_t np = (uint64_t)1 << (n - 2);
-  hipLaunchKernelGGL((k_apply_1q<float, f4, kV, kNT>), dim3(grid_for(np, kBlock * kV)),
-                     dim3(kBlock), 0, s->stream, (f4*)s->ptr, np, k - 1, m);
+  if (k == 0) go_inner<kNone>(s, 1ull << (n - 1), 0, m);
+  else units_1q<float, f4>(s, n - 1, k - 1, m);
   return last_launch("apply_1q c64");
 }
 
 Status launch_apply_cu(StateImpl* s, int c, int t, const double* q) {
   const int n = s->n;
   if (s->dtype == QS_C128) {
-    const uint64_t nq = (uint64_t)1 << (n - 2);
-    hipLaunchKernelGGL((k_apply_cu<double, d2, kV, kNT>), dim3(grid_for(nq, kBlock * kV)),
-                       dim3(kBlock), 0, s->stream, (d2*)s->ptr, nq, c, t, to_mat<double>(q));
+    units_cu<double, d2>(s, n, c, t, to_mat<double>(q));
     return last_launch("apply_cu c128");
   }
   const Mat<float> m = to_mat<float>(q);
-  if (t == 0) {
-    const uint64_t nsel = (uint64_t)1 << (n - 2);
-    hipLaunchKernelGGL((k_apply_cu_inner<kV, kNT>), dim3(grid_for(nsel, kBlock * kV)),
-                       dim3(kBlock), 0, s->stream, (f4*)s->ptr, nsel, c - 1, m);
-    return last_launch("apply_cu c64 inner");
+  const int u = n - 1;
+  if (t == 0) {  // pair inside each unit; control unit bit c - 1
+    const int cv = c - 1;
+    if (cv >= kLineUnitBits) go_inner<kCompact>(s, 1ull << (u - 1), cv, m);
+    else go_inner<kPred>(s, 1ull << u, cv, m);
+  } else if (c == 0) {  // control inside each unit: update odd amplitudes only
+    const int tv = t - 1;
+    if (tv < kExchangeBits) go_exchange<float, f4, kInnerCtrl>(s, 1ull << u, tv, 0, m);
+    else go_pair<float, f4, kInnerCtrl, 0>(s, 1ull << (u - 1), tv, 0, m);
+  } else {
+    units_cu<float, f4>(s, u, c - 1, t - 1, m);
   }
-  if (c == 0) {
-    // Control inside a vector: single 8-byte amplitudes.
-    const uint64_t nq = (uint64_t)1 << (n - 2);
-    hipLaunchKernelGGL((k_apply_cu<float, f2, kV, kNT>), dim3(grid_for(nq, kBlock * kV)),
-                       dim3(kBlock), 0, s->stream, (f2*)s->ptr, nq, c, t, m);
-    return last_launch("apply_cu c64 c0");
-  }
-  const uint64_t nq = (uint64_t)1 << (n - 3);
-  hipLaunchKernelGGL((k_apply_cu<float, f4, kV, kNT>), dim3(grid_for(nq, kBlock * kV)),
-                     dim3(kBlock), 0, s->stream, (f4*)s->ptr, nq, c - 1, t - 1, m);
   return last_launch("apply_cu c64");
+}
+
+Status launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t stream) {
+  const uint64_t nwords = bytes / 16;
+  if (nwords == 0) return Status::ok();
+  hipLaunchKernelGGL((k_stream_copy<kPairBlock>), dim3(grid_for(nwords, kPairBlock)),
+                     dim3(kPairBlock), 0, stream, (const u64x2*)src, (u64x2*)dst, nwords);
+  return last_launch("stream_copy");
 }
 
 }  // namespace qs

@@ -63,6 +63,7 @@ Status upload_table(StateImpl* s, const void* src, size_t bytes);
 Status launch_init_basis(StateImpl* s, uint64_t index);
 Status launch_apply_1q(StateImpl* s, int k, const double* q);
 Status launch_apply_cu(StateImpl* s, int c, int t, const double* q);
+Status launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t stream);
 
 // ------------------------------------------------------------ reductions
 // Per-qubit P(bit = 1), total norm^2 and optionally the full |a_i|^2 vector.

@@ -33,7 +33,8 @@ QS_OP_DTYPE = np.dtype([("kind", "<i4"), ("target", "<i4"), ("control", "<i4"),
 
 EXPORTED = ("qs_version", "qs_strerror", "qs_last_error", "qs_create", "qs_destroy",
             "qs_set_stream", "qs_init_basis", "qs_apply_1q", "qs_apply_cu", "qs_run",
-            "qs_probabilities", "qs_expect_pauli", "qs_apply_pauli_sum", "qs_grad_adjoint")
+            "qs_probabilities", "qs_expect_pauli", "qs_apply_pauli_sum", "qs_grad_adjoint",
+            "qs_stream_copy")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1601_07195_amd.build`")
@@ -56,6 +57,7 @@ _L.qs_probabilities.argtypes = [_vp, _dp, _dp, _vp, _sz]
 _L.qs_expect_pauli.argtypes = [_vp, _i, _vp, _vp, _dp, _dp]
 _L.qs_apply_pauli_sum.argtypes = [_vp, _vp, _i, _vp, _vp, _dp]
 _L.qs_grad_adjoint.argtypes = [_vp, _vp, _i, _dp, _i, _i, _vp, _vp, _dp, _vp, _i, _dp, _dp]
+_L.qs_stream_copy.argtypes = [_vp, _vp, _sz, _vp]
 for _name in EXPORTED:
     if _name not in ("qs_strerror", "qs_last_error"):
         getattr(_L, _name).restype = _i
@@ -211,6 +213,14 @@ def qs_grad_adjoint(h: int, ops, theta, x, z, coeff, lam: int, flags: int = 0):
     _check(_L.qs_grad_adjoint(h, _ptr(a), len(a), _ptr(th), len(th), len(c), _ptr(x), _ptr(z),
                               _ptr(c), lam, flags, _ptr(e), _ptr(g)), "qs_grad_adjoint")
     return float(e[0]), g
+
+
+def qs_stream_copy(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nbytes:
+        raise ValueError("dst smaller than src")
+    _check(_L.qs_stream_copy(src.data_ptr(), dst.data_ptr(), nbytes, _stream_handle(stream)),
+           "qs_stream_copy")
 
 
 # ------------------------------------------------------------ conveniences

@@ -167,3 +167,32 @@ def test_argument_errors_queue_nothing(Q):
     with pytest.raises(Q.QSError):
         st.run(bad)
     assert np.array_equal(st.numpy(), psi)
+
+
+@pytest.mark.parametrize("name,n", [("c128", 24), ("c64", 25)])
+def test_dispatch_shapes_at_large_n(Q, name, n):
+    """Every kernel shape the dispatcher picks (exchange by shuffle and by
+    LDS, paired streams in both workgroup orders, compact / predicated /
+    in-unit controls) at a size where the high-stride rules apply."""
+    rng = np.random.default_rng(500 + n)
+    psi = random_state(n, rng)
+    st = to_gpu_state(Q, psi, dt(Q, name))
+    ref = rounded_input(psi, name == "c64")
+    gates = [("1q", k) for k in (0, 1, 5, 6, 7, 8, 9, 21, 22, 23, 24, n - 1)] + \
+        [("cu", ct) for ct in ((0, n - 1), (n - 1, 0), (1, 2), (2, 9), (3, 22), (4, 23),
+                               (7, 10), (8, 6), (10, 7), (23, 3), (9, 20), (20, 9), (5, 6),
+                               (6, 5), (12, 1))]
+    for kind, arg in gates:
+        u = C.haar_unitary(rng)
+        if kind == "1q":
+            if arg >= n:
+                continue
+            st.apply_1q(arg, u)
+            O.apply_1q(ref, n, arg, u)
+        else:
+            c, t = arg
+            st.apply_cu(c, t, u)
+            O.apply_cu(ref, n, c, t, u)
+    got = st.numpy()
+    bound = TOL128 if name == "c128" else 2e-6
+    assert np.abs(got - ref).max() <= bound
