@@ -204,6 +204,32 @@ int qs_grad_adjoint(qs_state* s, const qs_op* ops, int nops,
                     qs_state* lambda, int flags, double* energy, double* grad);
 
 /*
+ * How qs_run would execute a gate list on an n-qubit state of `dtype`
+ * (no GPU work; host only).  The planner groups gates into passes over the
+ * state -- the GPU form of cache blocking by gate fusion, Sec. 4.4 -- and
+ * this reports the result:
+ *   info     host, filled with the counts below (may be NULL)
+ *   order    host, nops int32 or NULL: gate indices in execution order
+ *            (gates only move past gates they commute with)
+ *   pass_of  host, nops int32 or NULL: the pass that applies each gate
+ * hbm_bytes counts algorithmic HBM traffic as Table 2 does: a pass that
+ * rewrites the state moves 2 * 2^n * b bytes, a controlled gate run alone
+ * 2^n * b (b = bytes per amplitude).
+ */
+typedef struct qs_plan_info {
+  int32_t passes;       /* passes over the state in total */
+  int32_t fused;        /* passes applying several gates in one round trip */
+  int32_t single_1q;    /* single-qubit gates run as their own pass */
+  int32_t single_cu;    /* controlled gates run as their own pass */
+  int32_t remaps;       /* on-chip register remaps inside fused passes */
+  int32_t reserved;
+  double hbm_bytes;     /* algorithmic HBM bytes of the whole list */
+} qs_plan_info;
+int qs_plan(int n, int dtype, const qs_op* ops, int nops, const double* theta,
+            int nparams, int flags, qs_plan_info* info, int32_t* order,
+            int32_t* pass_of);
+
+/*
  * STREAM copy, dst[i] = src[i]: the sustainable-bandwidth probe that the
  * paper's lower bounds are stated against (Sec. 5.2, B_mem "measured by
  * STREAM Copy").  src, dst: device, 16-byte aligned, non-overlapping;

@@ -22,7 +22,8 @@ LIB = os.path.join(HERE, "libqs.so")
 OBJDIR = os.path.join(HERE, "_build")
 ARCH = "gfx950"
 
-SOURCES = ["qs_api.cpp", "qs_gates.hip", "qs_reduce.hip", "qs_circuit.hip", "qs_adjoint.hip"]
+SOURCES = ["qs_api.cpp", "qs_plan.cpp", "qs_gates.hip", "qs_reduce.hip", "qs_fused.hip",
+           "qs_adjoint.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{INCLUDE}", f"-I{CSRC}", "-Wall"]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

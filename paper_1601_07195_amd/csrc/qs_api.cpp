@@ -356,6 +356,43 @@ int qs_grad_adjoint(qs_state* s, const qs_op* ops, int nops, const double* theta
   return done(qs::run_adjoint(&s->impl, &lambda->impl, gates, nparams, t, flags, energy, grad));
 }
 
+int qs_plan(int n, int dtype, const qs_op* ops, int nops, const double* theta, int nparams,
+            int flags, qs_plan_info* info, int32_t* order, int32_t* pass_of) {
+  if (dtype != QS_C64 && dtype != QS_C128) return fail(QS_EINVAL, "qs_plan: bad dtype");
+  if (n < 1 || n > max_qubits(dtype)) return fail(QS_ERANGE, "qs_plan: n out of range");
+  if (nops < 0 || (nops > 0 && !ops)) return fail(QS_EINVAL, "qs_plan: bad op list");
+  if (nparams < 0) return fail(QS_EINVAL, "qs_plan: nparams < 0");
+  if (flags & ~QS_RUN_NO_FUSION) return fail(QS_EINVAL, "qs_plan: unknown flags");
+  std::vector<qs::XGate> gates;
+  Status st = qs::normalize_ops(n, ops, nops, theta, nparams, &gates);
+  if (!st.good()) return done(st);
+  qs::Plan plan;
+  qs::plan_gates(n, dtype, gates, !(flags & QS_RUN_NO_FUSION), &plan);
+  if (info) {
+    memset(info, 0, sizeof(*info));
+    const double S = (double)((size_t)1 << n) * (double)qs::amp_bytes(dtype);
+    for (const qs::Pass& p : plan.passes) {
+      ++info->passes;
+      if (p.kind == qs::kPassFused) {
+        ++info->fused;
+        info->remaps += p.remaps;
+        info->hbm_bytes += 2 * S;
+      } else if (p.kind == qs::kPass1q) {
+        ++info->single_1q;
+        info->hbm_bytes += 2 * S;
+      } else {
+        ++info->single_cu;
+        info->hbm_bytes += S;
+      }
+    }
+  }
+  for (int g = 0; g < nops; ++g) {
+    if (order) order[g] = plan.order[g];
+    if (pass_of) pass_of[g] = plan.pass_of[g];
+  }
+  return QS_OK;
+}
+
 int qs_stream_copy(const void* src, void* dst, size_t bytes, void* stream) {
   if (!src || !dst) return fail(QS_EINVAL, "qs_stream_copy: NULL pointer");
   if ((((uintptr_t)src) | ((uintptr_t)dst) | bytes) & 15)

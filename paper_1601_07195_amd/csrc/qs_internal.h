@@ -107,6 +107,61 @@ Status normalize_ops(int n, const qs_op* ops, int nops, const double* theta, int
                      std::vector<XGate>* out);
 Status run_gates(StateImpl* s, const std::vector<XGate>& gates, int flags);
 
+// ------------------------------------------------------- fusion planning
+// A fused pass keeps one tile of 2^T amplitudes on chip per workgroup: the
+// kLaneQ low qubits (coalesced) plus high qubits chosen per pass.  Each of
+// the 256 threads holds 2^NREG amplitudes in registers: its 8 thread-index
+// bits and NREG register-index bits are mapped to tile bits by an FMap.
+constexpr int kFuseThreadBits = 8;
+struct FuseGeom {
+  int nreg;   // register bits per thread (4 for complex128, 5 for complex64)
+  int T;      // tile bits = nreg + 8
+  int L;      // low qubits always in the tile (6 for complex128, 7 for complex64)
+  int lane0;  // first lane tile bit (0 for complex128; 1 for complex64, whose
+              // tile bit 0 is inside the 16-byte unit)
+};
+FuseGeom fuse_geom(int dtype);
+
+struct FMap {
+  int8_t thr[8];  // tile bit held by thread-index bit i
+  int8_t reg[5];  // tile bit held by register-index bit k (nreg used)
+  int8_t pad[3];
+};
+
+// Bit "spec": where a qubit currently lives for a fused op.
+enum SpecWhere { kInReg = 0, kInThread = 1, kOutside = 2, kNoBit = 3 };
+inline int32_t make_spec(int where, int index) { return (where << 8) | index; }
+
+enum FOpKind { kOpRemap = 0, kOpU = 1, kOpDiag = 2 };
+struct FOp {
+  int32_t kind;
+  int32_t tgt;   // kOpU: register bit; kOpDiag: spec of the target; kOpRemap: new FMap index
+  int32_t ctl;   // spec of the control (kNoBit when none)
+  int32_t aux;   // kOpRemap: old FMap index; adjoint: gradient slot or -1
+  double m[8];   // kOpU: the 2x2; kOpDiag: d0 = (m[0], m[1]), d1 = (m[6], m[7])
+};
+
+enum PassKind { kPassFused = 0, kPass1q = 1, kPassCU = 2 };
+struct Pass {
+  int kind;
+  int gate;          // streaming passes: index of the gate
+  int op_first, nops;  // fused: range in Plan::ops
+  int map_load, map_store;
+  int nh;            // fused: number of high tile qubits
+  int8_t hpos[8];    // fused: the high tile qubits, ascending
+  int remaps;
+};
+struct Plan {
+  std::vector<Pass> passes;
+  std::vector<FOp> ops;
+  std::vector<FMap> maps;
+  std::vector<int> order;  // gate indices in execution order
+  std::vector<int> pass_of;  // pass of each gate (by gate index)
+};
+// Plan `gates` (applied in list order) for an n-qubit state of `dtype`.
+void plan_gates(int n, int dtype, const std::vector<XGate>& gates, bool fuse, Plan* out);
+bool gate_is_diagonal(const XGate& g);
+
 // ----------------------------------------------------------- adjoint
 Status run_adjoint(StateImpl* s, StateImpl* lam, const std::vector<XGate>& gates,
                    int nparams, const PauliTable& h, int flags, double* energy, double* grad);

@@ -1,0 +1,322 @@
+// qs_plan.cpp -- the fusion planner (host only).
+//
+// Cache blocking by gate fusion (qHiPSTER Sec. 4.4, Fig. 4) re-planned for a
+// GPU: instead of one last-level-cache block of the low qubits, every pass
+// picks its own tile -- the low qubits (for coalesced HBM access) plus up to
+// six high qubits -- and takes as many gates as fit, so that the state makes
+// one HBM round trip per pass instead of one per gate.
+//
+// Which gates a pass can take:
+//   * a non-diagonal gate needs its target in the tile (its control may be
+//     anywhere: outside the tile it is a per-tile predicate);
+//   * a diagonal gate (controlled phases, RZ, ...) fits any pass: on a
+//     qubit outside the tile it is a per-tile scalar.
+// Gates are taken in order, and a later gate may move ahead of gates left
+// for a later pass only if it commutes with each of them.  Two gates commute
+// here when every qubit they share is acted on diagonally by both (a control
+// acts diagonally; so does the target of a diagonal gate) -- a sufficient
+// condition, exact in arithmetic.
+//
+// Inside a pass, non-diagonal gates act on register bits; the planner tracks
+// which tile bits sit in registers and inserts an on-chip remap (through LDS)
+// when a gate's target is not one of them, choosing the next register set as
+// the targets needed soonest.
+#include <algorithm>
+#include <cstring>
+
+#include "qs_internal.h"
+
+namespace qs {
+
+FuseGeom fuse_geom(int dtype) {
+  FuseGeom g;
+  if (dtype == QS_C128) {
+    g.nreg = 4;
+    g.L = 6;
+    g.lane0 = 0;
+  } else {
+    g.nreg = 5;
+    g.L = 7;
+    g.lane0 = 1;
+  }
+  g.T = g.nreg + kFuseThreadBits;
+  return g;
+}
+
+bool gate_is_diagonal(const XGate& g) {
+  return g.m[2] == 0.0 && g.m[3] == 0.0 && g.m[4] == 0.0 && g.m[5] == 0.0;
+}
+
+namespace {
+
+constexpr int kWindow = 512;     // gates scanned ahead for one pass
+constexpr int kMaxSkipped = 96;  // stop scanning once this many gates wait
+
+// Per-qubit action of a gate: 0 = none, 1 = diagonal, 2 = non-diagonal.
+struct Footprint {
+  int q[2];
+  int act[2];
+  int nq;
+};
+
+Footprint footprint(const XGate& g) {
+  Footprint f;
+  f.nq = 0;
+  const bool diag = gate_is_diagonal(g);
+  f.q[f.nq] = g.target;
+  f.act[f.nq++] = diag ? 1 : 2;
+  if (g.control >= 0) {
+    f.q[f.nq] = g.control;
+    f.act[f.nq++] = 1;
+  }
+  return f;
+}
+
+bool commute(const Footprint& a, const Footprint& b) {
+  for (int i = 0; i < a.nq; ++i)
+    for (int j = 0; j < b.nq; ++j)
+      if (a.q[i] == b.q[j] && (a.act[i] == 2 || b.act[j] == 2)) return false;
+  return true;
+}
+
+// Global qubit held by tile bit tb.
+inline int tile_qubit(int tb, int L, const std::vector<int>& hq) { return tb < L ? tb : hq[tb - L]; }
+
+struct Mapping {
+  int thr[8];
+  int reg[5];
+};
+
+bool same_lanes(const Mapping& a, const Mapping& b) {
+  for (int i = 0; i < 6; ++i)
+    if (a.thr[i] != b.thr[i]) return false;
+  return true;
+}
+
+FMap to_fmap(const Mapping& m) {
+  FMap f;
+  std::memset(&f, 0, sizeof(f));
+  for (int i = 0; i < 8; ++i) f.thr[i] = (int8_t)m.thr[i];
+  for (int k = 0; k < 5; ++k) f.reg[k] = (int8_t)m.reg[k];
+  return f;
+}
+
+}  // namespace
+
+void plan_gates(int n, int dtype, const std::vector<XGate>& gates, bool fuse, Plan* out) {
+  out->passes.clear();
+  out->ops.clear();
+  out->maps.clear();
+  out->order.clear();
+  const int N = (int)gates.size();
+  out->pass_of.assign(N, -1);
+  const FuseGeom G = fuse_geom(dtype);
+
+  auto stream_pass = [&](int g) {
+    Pass p;
+    std::memset(&p, 0, sizeof(p));
+    p.kind = gates[g].control >= 0 ? kPassCU : kPass1q;
+    p.gate = g;
+    out->pass_of[g] = (int)out->passes.size();
+    out->order.push_back(g);
+    out->passes.push_back(p);
+  };
+
+  if (!fuse || n < G.T) {
+    for (int g = 0; g < N; ++g) stream_pass(g);
+    return;
+  }
+
+  std::vector<Footprint> fp(N);
+  std::vector<char> diag(N);
+  for (int g = 0; g < N; ++g) {
+    fp[g] = footprint(gates[g]);
+    diag[g] = gate_is_diagonal(gates[g]);
+  }
+  std::vector<char> done(N, 0);
+  const int slots = G.T - G.L;
+  int start = 0;
+  while (start < N) {
+    // ---- choose the gates of this pass
+    std::vector<int> take;
+    std::vector<int> skipped;
+    std::vector<int> high;  // high tile qubits (unsorted while collecting)
+    auto in_tile = [&](int q) {
+      return q < G.L || std::find(high.begin(), high.end(), q) != high.end();
+    };
+    for (int g = start; g < N && g < start + kWindow; ++g) {
+      if (done[g]) continue;
+      bool blocked = false;
+      for (int s : skipped)
+        if (!commute(fp[g], fp[s])) {
+          blocked = true;
+          break;
+        }
+      if (!blocked) {
+        const int t = gates[g].target;
+        if (diag[g] || in_tile(t)) {
+          take.push_back(g);
+          continue;
+        }
+        if ((int)high.size() < slots) {
+          high.push_back(t);
+          take.push_back(g);
+          continue;
+        }
+      }
+      skipped.push_back(g);
+      if ((int)skipped.size() >= kMaxSkipped) break;
+    }
+    for (int g : take) done[g] = 1;
+    while (start < N && done[start]) ++start;
+
+    int nondiag = 0;
+    for (int g : take) nondiag += !diag[g];
+    if (take.size() == 1) {  // one gate: the streaming kernels are as cheap or cheaper
+      stream_pass(take[0]);
+      continue;
+    }
+
+    // ---- tile: fill the free high slots with the lowest unused qubits
+    for (int q = G.L; q < n && (int)high.size() < slots; ++q)
+      if (!in_tile(q)) high.push_back(q);
+    std::sort(high.begin(), high.end());
+    int tile_bit_of[64];
+    for (int q = 0; q < 64; ++q) tile_bit_of[q] = -1;
+    for (int q = 0; q < G.L; ++q) tile_bit_of[q] = q;
+    for (int h = 0; h < slots; ++h) tile_bit_of[high[h]] = G.L + h;
+
+    // ---- register allocation
+    // Lanes (thread bits 0..5) always start and end on tile bits lane0 ..
+    // lane0 + 5 (coalesced); complex64 keeps tile bit 0 in register bit 0 at
+    // load and store (it lives inside the 16-byte unit).
+    const int free0 = G.lane0 + 6;  // first tile bit that is neither lane nor in-unit
+    std::vector<int> targets;        // tile bit of each non-diagonal gate, in order
+    for (int g : take)
+      if (!diag[g]) targets.push_back(tile_bit_of[gates[g].target]);
+
+    Mapping cur;
+    for (int i = 0; i < 6; ++i) cur.thr[i] = G.lane0 + i;
+    {
+      // registers (beyond the in-unit bit) and wave bits from the free bits,
+      // preferring the first free-bit targets of the pass
+      std::vector<int> pick;
+      for (int tb : targets)
+        if (tb >= free0 && std::find(pick.begin(), pick.end(), tb) == pick.end() &&
+            (int)pick.size() < G.nreg - G.lane0)
+          pick.push_back(tb);
+      for (int tb = free0; tb < G.T && (int)pick.size() < G.nreg - G.lane0; ++tb)
+        if (std::find(pick.begin(), pick.end(), tb) == pick.end()) pick.push_back(tb);
+      int k = 0;
+      if (G.lane0 == 1) cur.reg[k++] = 0;
+      for (int tb : pick) cur.reg[k++] = tb;
+      for (; k < 5; ++k) cur.reg[k] = -1;
+      int w = 6;
+      for (int tb = free0; tb < G.T; ++tb)
+        if (std::find(pick.begin(), pick.end(), tb) == pick.end()) cur.thr[w++] = tb;
+    }
+    const Mapping load = cur;
+
+    Pass p;
+    std::memset(&p, 0, sizeof(p));
+    p.kind = kPassFused;
+    p.op_first = (int)out->ops.size();
+    p.map_load = (int)out->maps.size();
+    out->maps.push_back(to_fmap(load));
+    p.nh = slots;
+    for (int h = 0; h < slots; ++h) p.hpos[h] = (int8_t)high[h];
+
+    auto where = [&](const Mapping& m, int q) -> int32_t {
+      const int tb = tile_bit_of[q];
+      if (tb < 0) return make_spec(kOutside, q);
+      for (int k = 0; k < G.nreg; ++k)
+        if (m.reg[k] == tb) return make_spec(kInReg, k);
+      for (int i = 0; i < 8; ++i)
+        if (m.thr[i] == tb) return make_spec(kInThread, i);
+      return make_spec(kOutside, q);  // unreachable: every tile bit is mapped
+    };
+    auto emit_remap = [&](const Mapping& to) {
+      FOp op;
+      std::memset(&op, 0, sizeof(op));
+      op.kind = kOpRemap;
+      op.aux = (int)out->maps.size() - 1;  // the current mapping is the last pushed
+      out->maps.push_back(to_fmap(to));
+      op.tgt = (int)out->maps.size() - 1;
+      op.ctl = make_spec(kNoBit, 0);
+      out->ops.push_back(op);
+      ++p.remaps;
+    };
+
+    int ti = 0;  // index into targets
+    for (int g : take) {
+      const XGate& x = gates[g];
+      FOp op;
+      std::memset(&op, 0, sizeof(op));
+      std::memcpy(op.m, x.m, sizeof(op.m));
+      op.aux = -1;
+      if (diag[g]) {
+        op.kind = kOpDiag;
+        op.tgt = where(cur, x.target);
+      } else {
+        const int tb = targets[ti];
+        int rk = -1;
+        for (int k = 0; k < G.nreg; ++k)
+          if (cur.reg[k] == tb) rk = k;
+        if (rk < 0) {
+          // New register set: the distinct targets needed soonest, then the
+          // current registers, in that order of preference.
+          std::vector<int> want;
+          for (int j = ti; j < (int)targets.size() && (int)want.size() < G.nreg; ++j)
+            if (std::find(want.begin(), want.end(), targets[j]) == want.end())
+              want.push_back(targets[j]);
+          for (int k = 0; k < G.nreg && (int)want.size() < G.nreg; ++k)
+            if (std::find(want.begin(), want.end(), cur.reg[k]) == want.end())
+              want.push_back(cur.reg[k]);
+          Mapping nm = cur;
+          // registers keep their slot when they stay; newcomers take the
+          // slots of leavers, and leavers take the thread slots of newcomers
+          std::vector<int> leave, enter;
+          for (int k = 0; k < G.nreg; ++k)
+            if (std::find(want.begin(), want.end(), cur.reg[k]) == want.end()) leave.push_back(k);
+          for (int tbw : want) {
+            bool isreg = false;
+            for (int k = 0; k < G.nreg; ++k) isreg |= cur.reg[k] == tbw;
+            if (!isreg) enter.push_back(tbw);
+          }
+          for (size_t e = 0; e < enter.size(); ++e) {
+            const int k = leave[e];
+            const int old_tb = cur.reg[k];
+            int ti_slot = -1;
+            for (int i = 0; i < 8; ++i)
+              if (cur.thr[i] == enter[e]) ti_slot = i;
+            nm.reg[k] = enter[e];
+            nm.thr[ti_slot] = old_tb;
+          }
+          emit_remap(nm);
+          cur = nm;
+          for (int k = 0; k < G.nreg; ++k)
+            if (cur.reg[k] == tb) rk = k;
+        }
+        op.kind = kOpU;
+        op.tgt = rk;
+        ++ti;
+      }
+      op.ctl = x.control >= 0 ? where(cur, x.control) : make_spec(kNoBit, 0);
+      out->pass_of[g] = (int)out->passes.size();
+      out->order.push_back(g);
+      out->ops.push_back(op);
+    }
+    // ---- store mapping: coalesced lanes, and (complex64) tile bit 0 in
+    // register bit 0; otherwise remap back to the load mapping
+    bool ok = same_lanes(cur, load) && (G.lane0 == 0 || cur.reg[0] == 0);
+    if (!ok) {
+      emit_remap(load);
+      cur = load;
+    }
+    p.map_store = (int)out->maps.size() - 1;
+    p.nops = (int)out->ops.size() - p.op_first;
+    out->passes.push_back(p);
+  }
+}
+
+}  // namespace qs

@@ -34,7 +34,7 @@ QS_OP_DTYPE = np.dtype([("kind", "<i4"), ("target", "<i4"), ("control", "<i4"),
 EXPORTED = ("qs_version", "qs_strerror", "qs_last_error", "qs_create", "qs_destroy",
             "qs_set_stream", "qs_init_basis", "qs_apply_1q", "qs_apply_cu", "qs_run",
             "qs_probabilities", "qs_expect_pauli", "qs_apply_pauli_sum", "qs_grad_adjoint",
-            "qs_stream_copy")
+            "qs_stream_copy", "qs_plan")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1601_07195_amd.build`")
@@ -58,6 +58,16 @@ _L.qs_expect_pauli.argtypes = [_vp, _i, _vp, _vp, _dp, _dp]
 _L.qs_apply_pauli_sum.argtypes = [_vp, _vp, _i, _vp, _vp, _dp]
 _L.qs_grad_adjoint.argtypes = [_vp, _vp, _i, _dp, _i, _i, _vp, _vp, _dp, _vp, _i, _dp, _dp]
 _L.qs_stream_copy.argtypes = [_vp, _vp, _sz, _vp]
+
+
+class QSPlanInfo(ctypes.Structure):
+    _fields_ = [("passes", ctypes.c_int32), ("fused", ctypes.c_int32),
+                ("single_1q", ctypes.c_int32), ("single_cu", ctypes.c_int32),
+                ("remaps", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("hbm_bytes", ctypes.c_double)]
+
+
+_L.qs_plan.argtypes = [_i, _i, _vp, _i, _dp, _i, _i, ctypes.POINTER(QSPlanInfo), _vp, _vp]
 for _name in EXPORTED:
     if _name not in ("qs_strerror", "qs_last_error"):
         getattr(_L, _name).restype = _i
@@ -213,6 +223,19 @@ def qs_grad_adjoint(h: int, ops, theta, x, z, coeff, lam: int, flags: int = 0):
     _check(_L.qs_grad_adjoint(h, _ptr(a), len(a), _ptr(th), len(th), len(c), _ptr(x), _ptr(z),
                               _ptr(c), lam, flags, _ptr(e), _ptr(g)), "qs_grad_adjoint")
     return float(e[0]), g
+
+
+def qs_plan(n: int, dtype: int, ops, theta=None, flags: int = 0):
+    """Host-only planning: returns (info dict, order, pass_of)."""
+    a = ops_array(ops)
+    th = _f64(theta) if theta is not None else None
+    info = QSPlanInfo()
+    order = np.zeros(len(a), dtype=np.int32)
+    pass_of = np.zeros(len(a), dtype=np.int32)
+    _check(_L.qs_plan(n, dtype, _ptr(a), len(a), _ptr(th), 0 if th is None else len(th), flags,
+                      ctypes.byref(info), _ptr(order), _ptr(pass_of)), "qs_plan")
+    d = {f: getattr(info, f) for f, _ in QSPlanInfo._fields_ if f != "reserved"}
+    return d, order, pass_of
 
 
 def qs_stream_copy(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
