@@ -40,27 +40,6 @@ static void dagger(const double* m, double* d) {
   d[6] = m[6]; d[7] = -m[7];
 }
 
-// Im(conj(l) * w)
-__device__ __forceinline__ double im_conj_mul(double lr, double li, double wr, double wi) {
-  return lr * wi - li * wr;
-}
-
-// Im<lambda|P|psi> restricted to one amplitude pair (index bit of the
-// rotation's qubit 0 / 1), P = X (1), Y (2) or Z (3).
-__device__ __forceinline__ double pair_grad(int pauli, double a0r, double a0i, double a1r,
-                                            double a1i, double l0r, double l0i, double l1r,
-                                            double l1i) {
-  double w0r, w0i, w1r, w1i;
-  if (pauli == 1) {         // X: (a1, a0)
-    w0r = a1r; w0i = a1i; w1r = a0r; w1i = a0i;
-  } else if (pauli == 2) {  // Y: (-i a1, i a0)
-    w0r = a1i; w0i = -a1r; w1r = -a0i; w1i = a0r;
-  } else {                  // Z: (a0, -a1)
-    w0r = a0r; w0i = a0i; w1r = -a1r; w1i = -a1i;
-  }
-  return im_conj_mul(l0r, l0i, w0r, w0i) + im_conj_mul(l1r, l1i, w1r, w1i);
-}
-
 // Reverse step of a rotation on qubit k: gradient partial, then U^dagger on
 // psi and lambda.  T is one amplitude (d2 or f2).
 template <typename R, typename T>
@@ -123,9 +102,16 @@ k_sum_rows(const double* __restrict__ part, int ncols, double* __restrict__ out)
 
 static Status last_launch(const char* what) { return hip_status(hipGetLastError(), what); }
 
+Status launch_sum_rows(StateImpl* s, const double* part, int nrows, int ncols, double* out) {
+  hipLaunchKernelGGL(k_sum_rows, dim3(nrows), dim3(kBlock), 0, s->stream, part, ncols, out);
+  return last_launch("sum rows");
+}
+
+// Unfused reverse sweep (states smaller than one fused tile): one launch per
+// gate; rotation r (in reverse order) leaves its partials in row r.
 template <typename R, typename T>
 static Status reverse_sweep(StateImpl* s, StateImpl* lam, const std::vector<XGate>& gates,
-                            double* part, int grid, int* nrot_out) {
+                            double* part, int grid) {
   const int n = s->n;
   int r = 0;
   for (int g = (int)gates.size() - 1; g >= 0; --g) {
@@ -149,7 +135,6 @@ static Status reverse_sweep(StateImpl* s, StateImpl* lam, const std::vector<XGat
     Status st = last_launch("adjoint step");
     if (!st.good()) return st;
   }
-  *nrot_out = r;
   return Status::ok();
 }
 
@@ -160,57 +145,68 @@ Status run_adjoint(StateImpl* s, StateImpl* lam, const std::vector<XGate>& gates
     st = run_gates(s, gates, 0);
     if (!st.good()) return st;
   }
-  // lambda = H psi_N (queued on the state's stream).
+  // lambda = H psi_N, queued on the state's stream.
   StateImpl lam_on_s = *lam;
   lam_on_s.stream = s->stream;
   st = launch_apply_pauli_sum(s, &lam_on_s, h);
   if (!st.good()) return st;
-
-  int nrot = 0;
-  for (const XGate& x : gates)
-    if (x.kind >= QS_OP_RX) ++nrot;
-  const uint64_t npairs = 1ull << (s->n - 1);
-  const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(kAdjGrid, (npairs + kBlock - 1) / kBlock));
-  // Layout of the reduction buffer: the head is the inner product's own
-  // scratch, then [rotation][grid] partials, nrot sums and 2 doubles for
-  // <psi|lambda>.
-  const size_t head = 2 * (size_t)kAdjGrid;
-  const size_t nd = head + (size_t)nrot * grid + nrot + 2;
-  st = ensure_dev(s, s->red, nd * sizeof(double));
+  // E = Re<psi_N|H psi_N> into the handle's small-result buffer.
+  st = ensure_dev(s, s->scal, 4 * sizeof(double));
   if (!st.good()) return st;
-  double* part = (double*)s->red.ptr + head;
-  double* sums = part + (size_t)nrot * grid;
-  double* ev = sums + nrot;
-  // Energy E = Re<psi_N|H psi_N>.  launch_inner_dev uses the head of the
-  // reduction buffer as its own scratch, so it runs before the sweep fills
-  // the partials.
+  double* ev = (double*)s->scal.ptr;
   st = launch_inner_dev(s, &lam_on_s, ev);
   if (!st.good()) return st;
 
-  int r = 0;
-  if (s->dtype == QS_C128)
-    st = reverse_sweep<double, d2>(s, &lam_on_s, gates, part, grid, &r);
-  else
-    st = reverse_sweep<float, f2>(s, &lam_on_s, gates, part, grid, &r);
+  // Reverse sweep: rows[i] is the gradient row (parameter) of sums[i].
+  std::vector<int> rows;
+  double* sums = nullptr;
+  if (s->n >= fuse_geom(s->dtype).T) {
+    std::vector<XGate> rev;
+    rev.reserve(gates.size());
+    for (int g = (int)gates.size() - 1; g >= 0; --g) {
+      XGate x = gates[g];
+      dagger(gates[g].m, x.m);
+      rev.push_back(x);
+    }
+    st = run_adjoint_fused(s, &lam_on_s, rev, &rows, &sums);
+    if (!st.good()) return st;
+  } else {
+    for (int g = (int)gates.size() - 1; g >= 0; --g)
+      if (gates[g].kind >= QS_OP_RX) rows.push_back(gates[g].param);
+    const int nrot = (int)rows.size();
+    const uint64_t npairs = 1ull << (s->n - 1);
+    const int grid =
+        (int)std::max<uint64_t>(1, std::min<uint64_t>(kAdjGrid, (npairs + kBlock - 1) / kBlock));
+    st = ensure_dev(s, s->red, ((size_t)nrot * grid + nrot + 2) * sizeof(double));
+    if (!st.good()) return st;
+    double* part = (double*)s->red.ptr;
+    sums = part + (size_t)nrot * grid;
+    if (s->dtype == QS_C128)
+      st = reverse_sweep<double, d2>(s, &lam_on_s, gates, part, grid);
+    else
+      st = reverse_sweep<float, f2>(s, &lam_on_s, gates, part, grid);
+    if (!st.good()) return st;
+    if (nrot > 0) {
+      st = launch_sum_rows(s, part, nrot, grid, sums);
+      if (!st.good()) return st;
+    }
+  }
+  const size_t nrows = rows.size();
+  st = ensure_result_host(s, (nrows + 2) * sizeof(double));
   if (!st.good()) return st;
-  if (nrot > 0) {
-    hipLaunchKernelGGL(k_sum_rows, dim3(nrot), dim3(kBlock), 0, s->stream, part, grid, sums);
-    st = last_launch("adjoint sums");
+  if (nrows > 0) {
+    st = hip_status(hipMemcpyAsync(s->result_host, sums, nrows * sizeof(double),
+                                   hipMemcpyDeviceToHost, s->stream), "adjoint copy");
     if (!st.good()) return st;
   }
-  st = ensure_result_host(s, (nrot + 2) * sizeof(double));
-  if (!st.good()) return st;
-  st = hip_status(hipMemcpyAsync(s->result_host, sums, (nrot + 2) * sizeof(double),
-                                 hipMemcpyDeviceToHost, s->stream), "adjoint copy");
+  st = hip_status(hipMemcpyAsync(s->result_host + nrows, ev, 2 * sizeof(double),
+                                 hipMemcpyDeviceToHost, s->stream), "energy copy");
   if (!st.good()) return st;
   st = hip_status(hipStreamSynchronize(s->stream), "adjoint sync");
   if (!st.good()) return st;
-  if (energy) *energy = s->result_host[nrot];
+  if (energy) *energy = s->result_host[nrows];
   for (int p = 0; p < nparams; ++p) grad[p] = 0.0;
-  int ri = 0;
-  for (int g = (int)gates.size() - 1; g >= 0; --g) {
-    if (gates[g].kind >= QS_OP_RX) grad[gates[g].param] += s->result_host[ri++];
-  }
+  for (size_t i = 0; i < nrows; ++i) grad[rows[i]] += s->result_host[i];
   return Status::ok();
 }
 

@@ -240,6 +240,7 @@ int qs_destroy(qs_state* s) {
     rc = fail(QS_EHIP, "qs_destroy: stream synchronisation failed");
   }
   if (m.red.ptr) (void)hipFree(m.red.ptr);
+  if (m.scal.ptr) (void)hipFree(m.scal.ptr);
   if (m.table.ptr) (void)hipFree(m.table.ptr);
   if (m.stage.host) (void)hipHostFree(m.stage.host);
   if (m.stage.done) (void)hipEventDestroy(m.stage.done);

@@ -124,6 +124,27 @@ __device__ __forceinline__ void pair_apply_odd(const Mat<float>& q, f4& x, f4& y
   y = f4{y.x, y.y, dr, di};
 }
 
+// Im(conj(l) * w)
+__device__ __forceinline__ double im_conj_mul(double lr, double li, double wr, double wi) {
+  return lr * wi - li * wr;
+}
+
+// Im<lambda|P|psi> restricted to one amplitude pair (target bit 0 / 1),
+// P = X (1), Y (2) or Z (3), in double precision.
+__device__ __forceinline__ double pair_grad(int pauli, double a0r, double a0i, double a1r,
+                                            double a1i, double l0r, double l0i, double l1r,
+                                            double l1i) {
+  double w0r, w0i, w1r, w1i;
+  if (pauli == 1) {         // X: (a1, a0)
+    w0r = a1r; w0i = a1i; w1r = a0r; w1i = a0i;
+  } else if (pauli == 2) {  // Y: (-i a1, i a0)
+    w0r = a1i; w0i = -a1r; w1r = -a0i; w1i = a0r;
+  } else {                  // Z: (a0, -a1)
+    w0r = a0r; w0i = a0i; w1r = -a1r; w1i = -a1i;
+  }
+  return im_conj_mul(l0r, l0i, w0r, w0i) + im_conj_mul(l1r, l1i, w1r, w1i);
+}
+
 // An amplitude of the storage type from double-precision parts.
 template <typename T>
 __device__ __forceinline__ T make_amp(double re, double im);

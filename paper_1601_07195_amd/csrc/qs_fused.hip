@@ -3,11 +3,12 @@
 // The GPU form of cache blocking by gate fusion (qHiPSTER Sec. 4.4, Fig. 4):
 // a workgroup loads one tile of 2^T amplitudes (the low qubits plus the
 // pass's high qubits, see qs_plan.cpp) into registers -- 2^NREG amplitudes
-// per thread -- applies every gate of the pass there, and writes the tile
-// back.  Register-bit gates are plain register arithmetic; a remap moves the
-// tile through LDS so that other tile bits become register bits; diagonal
-// gates scale each amplitude by the entry its target bit selects, wherever
-// that bit lives (register, thread index, or outside the tile).
+// per thread, 8 for complex128 and 16 for complex64 -- applies every gate of
+// the pass there, and writes the tile back.  Register-bit gates are plain
+// register arithmetic; a remap moves the tile through LDS so that other tile
+// bits become register bits; diagonal gates scale each amplitude by the
+// entry its target bit selects, wherever that bit lives (register, thread
+// index, or outside the tile).
 #include <string.h>
 
 #include <algorithm>
@@ -19,10 +20,23 @@ namespace qs {
 
 constexpr int kFuseBlock = 1 << kFuseThreadBits;  // 256
 
+// Per-pass kernel arguments: the tile's high qubits and, for the load and
+// store mappings, the global qubit selected by each thread-index bit and by
+// each register-index bit.
 struct FusedArgs {
   uint64_t ntiles;
-  int L, nh, nops, map_load, map_store;
+  int32_t L, nh, nops, ngrad;
   int8_t hpos[8];
+  int8_t ld_thr[8], st_thr[8];
+  int8_t ld_reg[8], st_reg[8];
+};
+
+// Device form of an FMap for LDS remaps: tile bit of thread-index bit i in
+// nibble i of thr_pack; tile-local offset of register index r in regoff[r].
+struct FMapDev {
+  uint32_t thr_pack;
+  uint32_t pad[3];
+  int32_t regoff[32];
 };
 
 template <typename R>
@@ -44,48 +58,37 @@ struct LdsAmp<float> {
   }
 };
 
-// Global qubit of tile bit tb.
-__device__ __forceinline__ int gq(int tb, const FusedArgs& A) {
-  return tb < A.L ? tb : A.hpos[tb - A.L];
-}
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Offsets of a mapping: the thread part (per thread) and the register part
-// for register index r (uniform), either as tile-local indices (LDS) or as
-// global amplitude offsets.
-template <int NREG>
-__device__ __forceinline__ uint64_t thr_off_global(const FMap& m, const FusedArgs& A) {
-  uint64_t o = 0;
+// Tile-local offset of this thread's bits under a packed mapping.
+__device__ __forceinline__ int thr_tile_off(uint32_t pack) {
+  int o = 0;
 #pragma unroll
   for (int i = 0; i < kFuseThreadBits; ++i)
-    o |= (uint64_t)((threadIdx.x >> i) & 1) << gq(m.thr[i], A);
+    o |= ((threadIdx.x >> i) & 1) << ((pack >> (4 * i)) & 15);
   return o;
 }
+// Global offset of this thread's bits (thread bit i selects qubit q[i]).
+__device__ __forceinline__ uint64_t thr_global_off(const int8_t* q) {
+  uint64_t o = 0;
+#pragma unroll
+  for (int i = 0; i < kFuseThreadBits; ++i) o |= (uint64_t)((threadIdx.x >> i) & 1) << q[i];
+  return o;
+}
+// Global offset of register index r (compile-time); register bit k selects
+// qubit q[k] (uniform): scalar arithmetic.
 template <int NREG>
-__device__ __forceinline__ uint64_t reg_off_global(const FMap& m, const FusedArgs& A, int r) {
+__device__ __forceinline__ uint64_t reg_global_off(const int8_t* q, int r) {
   uint64_t o = 0;
 #pragma unroll
   for (int k = 0; k < NREG; ++k)
-    if ((r >> k) & 1) o |= 1ull << gq(m.reg[k], A);
-  return o;
-}
-template <int NREG>
-__device__ __forceinline__ int thr_off_tile(const FMap& m) {
-  int o = 0;
-#pragma unroll
-  for (int i = 0; i < kFuseThreadBits; ++i) o |= ((threadIdx.x >> i) & 1) << m.thr[i];
-  return o;
-}
-template <int NREG>
-__device__ __forceinline__ int reg_off_tile(const FMap& m, int r) {
-  int o = 0;
-#pragma unroll
-  for (int k = 0; k < NREG; ++k)
-    if ((r >> k) & 1) o |= 1 << m.reg[k];
+    if ((r >> k) & 1) o |= 1ull << q[k];
   return o;
 }
 
-// Gate on register bit K for every register pair (r, r | 2^K), optionally
-// controlled by register bit creg.
+// Gate on register bit K for every register pair (r, r | 2^K); a control on
+// register bit creg (uniform, -1 for none) skips the pairs whose control bit
+// is 0 (a uniform branch: r is a compile-time constant).
 template <int K, int RA, typename R>
 __device__ __forceinline__ void reg_gate(R* re, R* im, const Mat<R>& q, int creg) {
 #pragma unroll
@@ -97,80 +100,178 @@ __device__ __forceinline__ void reg_gate(R* re, R* im, const Mat<R>& q, int creg
   }
 }
 
-template <typename R>
-__device__ __forceinline__ Mat<R> load_mat(const double* m) {
-  Mat<R> q;
+// Im<lambda|P|psi> over the register pairs of bit K (P = X or Y).
+template <int K, int RA, typename R>
+__device__ __forceinline__ double reg_grad(const R* re, const R* im, const R* lr, const R* li,
+                                           int pauli) {
+  double g = 0.0;
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    q.r[e] = (R)m[2 * e];
-    q.i[e] = (R)m[2 * e + 1];
+  for (int r = 0; r < RA; ++r) {
+    if (r & (1 << K)) continue;
+    const int r1 = r | (1 << K);
+    g += pair_grad(pauli, re[r], im[r], re[r1], im[r1], lr[r], li[r], lr[r1], li[r1]);
   }
-  return q;
+  return g;
 }
 
-// Apply ops[0 .. nops) to the register tile.  `base` is the tile's global
-// index base (bits outside the tile).
+// amplitude *= (dr + i di)
+template <typename R>
+__device__ __forceinline__ void cscale(R& xr, R& xi, R dr, R di) {
+  const R ar = dr * xr - di * xi;
+  xi = dr * xi + di * xr;
+  xr = ar;
+}
+
 template <typename R, int NREG>
-__device__ __forceinline__ void run_ops(R* re, R* im, typename LdsAmp<R>::T* lds,
-                                        const FOp* __restrict__ ops, int nops,
-                                        const FMap* __restrict__ maps, uint64_t base) {
+__device__ __forceinline__ void remap_tile(R* re, R* im, typename LdsAmp<R>::T* lds, int to,
+                                           const FMapDev* mo, int tn, const FMapDev* mn) {
   constexpr int RA = 1 << NREG;
   using LT = typename LdsAmp<R>::T;
-  for (int o = 0; o < nops; ++o) {
-    const FOp& op = ops[o];
-    const int kind = op.kind;
+#pragma unroll
+  for (int r = 0; r < RA; ++r) {
+    LT v;
+    v.x = re[r];
+    v.y = im[r];
+    lds[LdsAmp<R>::swz(to | mo->regoff[r])] = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < RA; ++r) {
+    const LT v = lds[LdsAmp<R>::swz(tn | mn->regoff[r])];
+    re[r] = v.x;
+    im[r] = v.y;
+  }
+  __syncthreads();
+}
+
+template <typename R, int NREG>
+__device__ __forceinline__ void reg_gate_any(R* re, R* im, const Mat<R>& q, int creg, int k) {
+  constexpr int RA = 1 << NREG;
+  switch (k) {
+    case 0: reg_gate<0, RA>(re, im, q, creg); break;
+    case 1: reg_gate<1, RA>(re, im, q, creg); break;
+    case 2: reg_gate<2, RA>(re, im, q, creg); break;
+    default:
+      if constexpr (NREG > 3) reg_gate<(NREG > 3 ? 3 : 0), RA>(re, im, q, creg);
+      break;
+  }
+}
+
+template <typename R, int NREG>
+__device__ __forceinline__ double reg_grad_any(const R* re, const R* im, const R* lr,
+                                               const R* li, int pauli, int k) {
+  constexpr int RA = 1 << NREG;
+  switch (k) {
+    case 0: return reg_grad<0, RA>(re, im, lr, li, pauli);
+    case 1: return reg_grad<1, RA>(re, im, lr, li, pauli);
+    case 2: return reg_grad<2, RA>(re, im, lr, li, pauli);
+    default:
+      if constexpr (NREG > 3) return reg_grad<(NREG > 3 ? 3 : 0), RA>(re, im, lr, li, pauli);
+      return 0.0;
+  }
+}
+
+// Diagonal op on one register tile: amplitude *= d0 or d1 by its target bit.
+template <typename R, int NREG>
+__device__ __forceinline__ void diag_tile(R* re, R* im, R d0r, R d0i, R d1r, R d1i, int tw,
+                                          int tix, int creg, bool on, uint64_t base) {
+  constexpr int RA = 1 << NREG;
+  if (tw == kInReg) {
+    // entries per register index: uniform, except for a thread control
+#pragma unroll
+    for (int r = 0; r < RA; ++r) {
+      const bool bit = (r >> tix) & 1;
+      const bool c_r = creg < 0 || ((r >> creg) & 1);
+      R dr = bit ? d1r : d0r, di = bit ? d1i : d0i;
+      dr = c_r ? dr : (R)1;
+      di = c_r ? di : (R)0;
+      dr = on ? dr : (R)1;
+      di = on ? di : (R)0;
+      cscale(re[r], im[r], dr, di);
+    }
+  } else {
+    // target bit fixed for the whole thread (thread bit) or tile (outside)
+    const bool bit = (tw == kInThread) ? (bool)((threadIdx.x >> tix) & 1)
+                                       : (bool)((base >> tix) & 1);
+    const R tr = on ? (bit ? d1r : d0r) : (R)1, ti = on ? (bit ? d1i : d0i) : (R)0;
+#pragma unroll
+    for (int r = 0; r < RA; ++r) {
+      const bool c_r = creg < 0 || ((r >> creg) & 1);  // uniform
+      cscale(re[r], im[r], c_r ? tr : (R)1, c_r ? ti : (R)0);
+    }
+  }
+}
+
+// Apply ops[0 .. nops) to the register tile(s).  `base` is the tile's
+// global index base (bits outside the tile).  The op index goes through
+// readfirstlane, so op records and mappings are fetched with scalar loads
+// and gate coefficients live in scalar registers.  Diagonal entries and
+// their controls are resolved into the coefficients (per register index when
+// uniform, once per thread for thread-index bits).
+//
+// ADJ: a second tile (lambda) receives every gate too, and ops with a
+// gradient slot first add Im<lambda|P|psi> (P = the rotation's generator,
+// X/Y on register pairs, Z by the sign of the target bit) to the wave's LDS
+// accumulator of that slot.
+template <typename R, int NREG, bool ADJ>
+__device__ __forceinline__ void run_ops(R* re, R* im, R* lre, R* lim,
+                                        typename LdsAmp<R>::T* lds, const FOp* __restrict__ ops,
+                                        int nops, const FMapDev* __restrict__ maps,
+                                        uint64_t base, double* acc) {
+  constexpr int RA = 1 << NREG;
+  for (int oi = 0; oi < nops; ++oi) {
+    const FOp* op = ops + uniform(oi);
+    const int kw = op->kind, tgt = op->tgt, ctl = op->ctl, aux = op->aux;
+    const int kind = kw & 255, pauli = kw >> 8;
     if (kind == kOpRemap) {
-      const FMap mo = maps[op.aux], mn = maps[op.tgt];
-      const int to = thr_off_tile<NREG>(mo), tn = thr_off_tile<NREG>(mn);
-#pragma unroll
-      for (int r = 0; r < RA; ++r) {
-        LT v;
-        v.x = re[r];
-        v.y = im[r];
-        lds[LdsAmp<R>::swz(to | reg_off_tile<NREG>(mo, r))] = v;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int r = 0; r < RA; ++r) {
-        const LT v = lds[LdsAmp<R>::swz(tn | reg_off_tile<NREG>(mn, r))];
-        re[r] = v.x;
-        im[r] = v.y;
-      }
-      __syncthreads();
+      const FMapDev* mo = maps + uniform(aux);
+      const FMapDev* mn = maps + uniform(tgt);
+      const int to = thr_tile_off(mo->thr_pack), tn = thr_tile_off(mn->thr_pack);
+      remap_tile<R, NREG>(re, im, lds, to, mo, tn, mn);
+      if constexpr (ADJ) remap_tile<R, NREG>(lre, lim, lds, to, mo, tn, mn);
       continue;
     }
-    const int cw = op.ctl >> 8, ci = op.ctl & 255;
-    bool on = true;
-    int creg = -1;
-    if (cw == kInThread) on = (threadIdx.x >> ci) & 1;
-    else if (cw == kOutside) on = (base >> ci) & 1;
-    else if (cw == kInReg) creg = ci;
-    if (!on) continue;
+    const int cw = ctl >> 8, ci = ctl & 255;
+    if (cw == kOutside && !((base >> ci) & 1)) continue;  // per-tile predicate (uniform)
+    const int creg = (cw == kInReg) ? ci : -1;
+    const bool on = (cw == kInThread) ? (bool)((threadIdx.x >> ci) & 1) : true;
     if (kind == kOpU) {
-      const Mat<R> q = load_mat<R>(op.m);
-      switch (op.tgt) {
-        case 0: reg_gate<0, RA>(re, im, q, creg); break;
-        case 1: reg_gate<1, RA>(re, im, q, creg); break;
-        case 2: reg_gate<2, RA>(re, im, q, creg); break;
-        case 3: reg_gate<3, RA>(re, im, q, creg); break;
-        default:
-          if constexpr (NREG > 4) reg_gate<(NREG > 4 ? 4 : 0), RA>(re, im, q, creg);
-          break;
+      Mat<R> q;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        q.r[e] = (R)op->m[2 * e];
+        q.i[e] = (R)op->m[2 * e + 1];
+      }
+      if constexpr (ADJ) {
+        if (aux >= 0) {  // rotation (never controlled): gradient before the inverse
+          const double g = wave_sum(reg_grad_any<R, NREG>(re, im, lre, lim, pauli, tgt));
+          if ((threadIdx.x & 63) == 0) acc[aux * 4 + (threadIdx.x >> 6)] += g;
+        }
+      }
+      if (on) {  // a thread-index control: the only lane-dependent branch
+        reg_gate_any<R, NREG>(re, im, q, creg, tgt);
+        if constexpr (ADJ) reg_gate_any<R, NREG>(lre, lim, q, creg, tgt);
       }
     } else {  // diagonal
-      const R d0r = (R)op.m[0], d0i = (R)op.m[1], d1r = (R)op.m[6], d1i = (R)op.m[7];
-      const int tw = op.tgt >> 8, tix = op.tgt & 255;
-      const int fixed = (tw == kInThread) ? (int)((threadIdx.x >> tix) & 1)
-                                          : (tw == kOutside ? (int)((base >> tix) & 1) : -1);
+      const R d0r = (R)op->m[0], d0i = (R)op->m[1], d1r = (R)op->m[6], d1i = (R)op->m[7];
+      const int tw = tgt >> 8, tix = tgt & 255;
+      if constexpr (ADJ) {
+        if (aux >= 0) {  // RZ: Im<lambda|Z|psi> = sum of +-Im(conj(l) a) by the target bit
+          double g = 0.0;
+          const bool fixed_bit = (tw == kInThread) ? (bool)((threadIdx.x >> tix) & 1)
+                                                   : (bool)((base >> tix) & 1);
 #pragma unroll
-      for (int r = 0; r < RA; ++r) {
-        if (creg >= 0 && !((r >> creg) & 1)) continue;
-        const int bit = fixed >= 0 ? fixed : ((r >> tix) & 1);
-        const R dr = bit ? d1r : d0r, di = bit ? d1i : d0i;
-        const R xr = re[r], xi = im[r];
-        re[r] = dr * xr - di * xi;
-        im[r] = dr * xi + di * xr;
+          for (int r = 0; r < RA; ++r) {
+            const bool bit = (tw == kInReg) ? (bool)((r >> tix) & 1) : fixed_bit;
+            const double t = im_conj_mul(lre[r], lim[r], re[r], im[r]);
+            g += bit ? -t : t;
+          }
+          g = wave_sum(g);
+          if ((threadIdx.x & 63) == 0) acc[aux * 4 + (threadIdx.x >> 6)] += g;
+        }
       }
+      diag_tile<R, NREG>(re, im, d0r, d0i, d1r, d1i, tw, tix, creg, on, base);
+      if constexpr (ADJ) diag_tile<R, NREG>(lre, lim, d0r, d0i, d1r, d1i, tw, tix, creg, on, base);
     }
   }
 }
@@ -181,28 +282,30 @@ __device__ __forceinline__ uint64_t tile_base(uint64_t tile, const FusedArgs& A)
   return x;
 }
 
+// One tile per workgroup (a one-shot grid overlaps the loads, arithmetic and
+// stores of different workgroups better than a persistent loop here).
+
 // complex128: one d2 per amplitude.
 template <int NREG>
 __global__ void __launch_bounds__(kFuseBlock)
 k_fused_c128(d2* __restrict__ a, FusedArgs A, const FOp* __restrict__ ops,
-             const FMap* __restrict__ maps) {
+             const FMapDev* __restrict__ maps) {
   constexpr int RA = 1 << NREG;
   __shared__ d2 lds[RA * kFuseBlock];
   double re[RA], im[RA];
-  const FMap ml = maps[A.map_load], ms = maps[A.map_store];
-  const uint64_t tl = thr_off_global<NREG>(ml, A), ts = thr_off_global<NREG>(ms, A);
+  const uint64_t tl = thr_global_off(A.ld_thr), ts = thr_global_off(A.st_thr);
   for (uint64_t tile = blockIdx.x; tile < A.ntiles; tile += gridDim.x) {
     const uint64_t base = tile_base(tile, A);
 #pragma unroll
     for (int r = 0; r < RA; ++r) {
-      const d2 v = gload<true>(a + (base | tl | reg_off_global<NREG>(ml, A, r)));
+      const d2 v = gload<true>(a + (base | tl | reg_global_off<NREG>(A.ld_reg, r)));
       re[r] = v.x;
       im[r] = v.y;
     }
-    run_ops<double, NREG>(re, im, lds, ops, A.nops, maps, base);
+    run_ops<double, NREG, false>(re, im, nullptr, nullptr, lds, ops, A.nops, maps, base, nullptr);
 #pragma unroll
     for (int r = 0; r < RA; ++r)
-      gstore<true>(a + (base | ts | reg_off_global<NREG>(ms, A, r)), d2{re[r], im[r]});
+      gstore<true>(a + (base | ts | reg_global_off<NREG>(A.st_reg, r)), d2{re[r], im[r]});
   }
 }
 
@@ -211,48 +314,171 @@ k_fused_c128(d2* __restrict__ a, FusedArgs A, const FOp* __restrict__ ops,
 template <int NREG>
 __global__ void __launch_bounds__(kFuseBlock)
 k_fused_c64(f4* __restrict__ a, FusedArgs A, const FOp* __restrict__ ops,
-            const FMap* __restrict__ maps) {
+            const FMapDev* __restrict__ maps) {
   constexpr int RA = 1 << NREG;
   __shared__ f2 lds[RA * kFuseBlock];
   float re[RA], im[RA];
-  const FMap ml = maps[A.map_load], ms = maps[A.map_store];
-  const uint64_t tl = thr_off_global<NREG>(ml, A), ts = thr_off_global<NREG>(ms, A);
+  const uint64_t tl = thr_global_off(A.ld_thr), ts = thr_global_off(A.st_thr);
   for (uint64_t tile = blockIdx.x; tile < A.ntiles; tile += gridDim.x) {
     const uint64_t base = tile_base(tile, A);
 #pragma unroll
     for (int r = 0; r < RA; r += 2) {
-      const f4 v = gload<true>(a + ((base | tl | reg_off_global<NREG>(ml, A, r)) >> 1));
+      const f4 v = gload<true>(a + ((base | tl | reg_global_off<NREG>(A.ld_reg, r)) >> 1));
       re[r] = v.x;
       im[r] = v.y;
       re[r + 1] = v.z;
       im[r + 1] = v.w;
     }
-    run_ops<float, NREG>(re, im, lds, ops, A.nops, maps, base);
+    run_ops<float, NREG, false>(re, im, nullptr, nullptr, lds, ops, A.nops, maps, base, nullptr);
 #pragma unroll
     for (int r = 0; r < RA; r += 2)
-      gstore<true>(a + ((base | ts | reg_off_global<NREG>(ms, A, r)) >> 1),
+      gstore<true>(a + ((base | ts | reg_global_off<NREG>(A.st_reg, r)) >> 1),
                    f4{re[r], im[r], re[r + 1], im[r + 1]});
   }
 }
 
+// ------------------------------------------------------------- adjoint
+// psi and lambda tiles side by side; a persistent grid so that every
+// workgroup folds its gradient contributions over many tiles into its LDS
+// slots and leaves one partial per slot: part[slot * gridDim.x + block].
+template <int NREG>
+__global__ void __launch_bounds__(kFuseBlock)
+k_fused_adj_c128(d2* __restrict__ psi, d2* __restrict__ lam, FusedArgs A,
+                 const FOp* __restrict__ ops, const FMapDev* __restrict__ maps,
+                 double* __restrict__ part) {
+  constexpr int RA = 1 << NREG;
+  __shared__ d2 lds[RA * kFuseBlock];
+  __shared__ double acc[kAdjMaxSlots * 4];
+  for (int i = threadIdx.x; i < kAdjMaxSlots * 4; i += kFuseBlock) acc[i] = 0.0;
+  __syncthreads();
+  double re[RA], im[RA], lre[RA], lim[RA];
+  const uint64_t tl = thr_global_off(A.ld_thr), ts = thr_global_off(A.st_thr);
+  for (uint64_t tile = blockIdx.x; tile < A.ntiles; tile += gridDim.x) {
+    const uint64_t base = tile_base(tile, A);
+#pragma unroll
+    for (int r = 0; r < RA; ++r) {
+      const uint64_t i = base | tl | reg_global_off<NREG>(A.ld_reg, r);
+      const d2 v = gload<true>(psi + i), w = gload<true>(lam + i);
+      re[r] = v.x;
+      im[r] = v.y;
+      lre[r] = w.x;
+      lim[r] = w.y;
+    }
+    run_ops<double, NREG, true>(re, im, lre, lim, lds, ops, A.nops, maps, base, acc);
+#pragma unroll
+    for (int r = 0; r < RA; ++r) {
+      const uint64_t i = base | ts | reg_global_off<NREG>(A.st_reg, r);
+      gstore<true>(psi + i, d2{re[r], im[r]});
+      gstore<true>(lam + i, d2{lre[r], lim[r]});
+    }
+  }
+  __syncthreads();
+  for (int sl = threadIdx.x; sl < A.ngrad; sl += kFuseBlock)
+    part[(size_t)sl * gridDim.x + blockIdx.x] =
+        acc[sl * 4] + acc[sl * 4 + 1] + acc[sl * 4 + 2] + acc[sl * 4 + 3];
+}
+
+template <int NREG>
+__global__ void __launch_bounds__(kFuseBlock)
+k_fused_adj_c64(f4* __restrict__ psi, f4* __restrict__ lam, FusedArgs A,
+                const FOp* __restrict__ ops, const FMapDev* __restrict__ maps,
+                double* __restrict__ part) {
+  constexpr int RA = 1 << NREG;
+  __shared__ f2 lds[RA * kFuseBlock];
+  __shared__ double acc[kAdjMaxSlots * 4];
+  for (int i = threadIdx.x; i < kAdjMaxSlots * 4; i += kFuseBlock) acc[i] = 0.0;
+  __syncthreads();
+  float re[RA], im[RA], lre[RA], lim[RA];
+  const uint64_t tl = thr_global_off(A.ld_thr), ts = thr_global_off(A.st_thr);
+  for (uint64_t tile = blockIdx.x; tile < A.ntiles; tile += gridDim.x) {
+    const uint64_t base = tile_base(tile, A);
+#pragma unroll
+    for (int r = 0; r < RA; r += 2) {
+      const uint64_t u = (base | tl | reg_global_off<NREG>(A.ld_reg, r)) >> 1;
+      const f4 v = gload<true>(psi + u), w = gload<true>(lam + u);
+      re[r] = v.x; im[r] = v.y; re[r + 1] = v.z; im[r + 1] = v.w;
+      lre[r] = w.x; lim[r] = w.y; lre[r + 1] = w.z; lim[r + 1] = w.w;
+    }
+    run_ops<float, NREG, true>(re, im, lre, lim, lds, ops, A.nops, maps, base, acc);
+#pragma unroll
+    for (int r = 0; r < RA; r += 2) {
+      const uint64_t u = (base | ts | reg_global_off<NREG>(A.st_reg, r)) >> 1;
+      gstore<true>(psi + u, f4{re[r], im[r], re[r + 1], im[r + 1]});
+      gstore<true>(lam + u, f4{lre[r], lim[r], lre[r + 1], lim[r + 1]});
+    }
+  }
+  __syncthreads();
+  for (int sl = threadIdx.x; sl < A.ngrad; sl += kFuseBlock)
+    part[(size_t)sl * gridDim.x + blockIdx.x] =
+        acc[sl * 4] + acc[sl * 4 + 1] + acc[sl * 4 + 2] + acc[sl * 4 + 3];
+}
+
+// Host: device tables of a plan's mappings.
+static FMapDev fmap_dev(const FMap& m, int nreg) {
+  FMapDev d;
+  memset(&d, 0, sizeof(d));
+  for (int i = 0; i < kFuseThreadBits; ++i) d.thr_pack |= (uint32_t)(m.thr[i] & 15) << (4 * i);
+  for (int r = 0; r < (1 << nreg); ++r) {
+    int o = 0;
+    for (int k = 0; k < nreg; ++k)
+      if ((r >> k) & 1) o |= 1 << m.reg[k];
+    d.regoff[r] = o;
+  }
+  return d;
+}
+
+// Host: global qubits of a mapping's thread and register bits for a pass
+// with low qubits L and high qubits hpos.
+static void fmap_global(const FMap& m, int nreg, int L, const int8_t* hpos, int8_t* thr,
+                        int8_t* reg) {
+  auto gq = [&](int tb) { return tb < L ? tb : (int)hpos[tb - L]; };
+  for (int i = 0; i < kFuseThreadBits; ++i) thr[i] = (int8_t)gq(m.thr[i]);
+  for (int k = 0; k < 8; ++k) reg[k] = (int8_t)(k < nreg ? gq(m.reg[k]) : 0);
+}
+
 static Status last_launch(const char* what) { return hip_status(hipGetLastError(), what); }
+
+// Upload a plan's ops and mapping tables into the state's table buffer.
+static Status upload_plan(StateImpl* s, const Plan& plan, const FuseGeom& G, const FOp** dops,
+                          const FMapDev** dmaps) {
+  *dops = nullptr;
+  *dmaps = nullptr;
+  if (plan.ops.empty()) return Status::ok();
+  std::vector<FMapDev> md;
+  for (const FMap& m : plan.maps) md.push_back(fmap_dev(m, G.nreg));
+  const size_t ob = plan.ops.size() * sizeof(FOp), mb = md.size() * sizeof(FMapDev);
+  std::vector<char> blob(ob + mb);
+  memcpy(blob.data(), plan.ops.data(), ob);
+  memcpy(blob.data() + ob, md.data(), mb);
+  Status st = upload_table(s, blob.data(), blob.size());
+  if (!st.good()) return st;
+  *dops = (const FOp*)s->table.ptr;
+  *dmaps = (const FMapDev*)((const char*)s->table.ptr + ob);
+  return Status::ok();
+}
+
+static FusedArgs pass_args(const StateImpl* s, const Plan& plan, const Pass& p, const FuseGeom& G) {
+  FusedArgs A;
+  memset(&A, 0, sizeof(A));
+  A.ntiles = 1ull << (s->n - G.T);
+  A.L = G.L;
+  A.nh = p.nh;
+  A.nops = p.nops;
+  A.ngrad = p.ngrad;
+  for (int h = 0; h < p.nh; ++h) A.hpos[h] = p.hpos[h];
+  fmap_global(plan.maps[p.map_load], G.nreg, G.L, p.hpos, A.ld_thr, A.ld_reg);
+  fmap_global(plan.maps[p.map_store], G.nreg, G.L, p.hpos, A.st_thr, A.st_reg);
+  return A;
+}
 
 Status run_gates(StateImpl* s, const std::vector<XGate>& gates, int flags) {
   Plan plan;
   plan_gates(s->n, s->dtype, gates, !(flags & QS_RUN_NO_FUSION), &plan);
-  const FOp* dops = nullptr;
-  const FMap* dmaps = nullptr;
-  if (!plan.ops.empty()) {
-    const size_t ob = plan.ops.size() * sizeof(FOp), mb = plan.maps.size() * sizeof(FMap);
-    std::vector<char> blob(ob + mb);
-    memcpy(blob.data(), plan.ops.data(), ob);
-    memcpy(blob.data() + ob, plan.maps.data(), mb);
-    Status st = upload_table(s, blob.data(), blob.size());
-    if (!st.good()) return st;
-    dops = (const FOp*)s->table.ptr;
-    dmaps = (const FMap*)((const char*)s->table.ptr + ob);
-  }
   const FuseGeom G = fuse_geom(s->dtype);
+  const FOp* dops;
+  const FMapDev* dmaps;
+  Status up = upload_plan(s, plan, G, &dops, &dmaps);
+  if (!up.good()) return up;
   for (const Pass& p : plan.passes) {
     Status st;
     if (p.kind == kPass1q) {
@@ -260,26 +486,73 @@ Status run_gates(StateImpl* s, const std::vector<XGate>& gates, int flags) {
     } else if (p.kind == kPassCU) {
       st = launch_apply_cu(s, gates[p.gate].control, gates[p.gate].target, gates[p.gate].m);
     } else {
-      FusedArgs A;
-      memset(&A, 0, sizeof(A));
-      A.ntiles = 1ull << (s->n - G.T);
-      A.L = G.L;
-      A.nh = p.nh;
-      A.nops = p.nops;
-      A.map_load = p.map_load;
-      A.map_store = p.map_store;
-      for (int h = 0; h < p.nh; ++h) A.hpos[h] = p.hpos[h];
+      const FusedArgs A = pass_args(s, plan, p, G);
       const unsigned grid = (unsigned)std::min<uint64_t>(A.ntiles, (1ull << 31) / kFuseBlock);
       if (s->dtype == QS_C128)
-        hipLaunchKernelGGL((k_fused_c128<4>), dim3(grid), dim3(kFuseBlock), 0, s->stream,
+        hipLaunchKernelGGL((k_fused_c128<3>), dim3(grid), dim3(kFuseBlock), 0, s->stream,
                            (d2*)s->ptr, A, dops + p.op_first, dmaps);
       else
-        hipLaunchKernelGGL((k_fused_c64<5>), dim3(grid), dim3(kFuseBlock), 0, s->stream,
+        hipLaunchKernelGGL((k_fused_c64<4>), dim3(grid), dim3(kFuseBlock), 0, s->stream,
                            (f4*)s->ptr, A, dops + p.op_first, dmaps);
       st = last_launch("fused pass");
     }
     if (!st.good()) return st;
   }
+  return Status::ok();
+}
+
+// Compute units of the state's device (queried once per handle).
+static int device_cus(StateImpl* s) {
+  if (s->cus <= 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, s->device) != hipSuccess ||
+        v <= 0) {
+      (void)hipGetLastError();
+      v = 256;
+    }
+    s->cus = v;
+  }
+  return s->cus;
+}
+
+constexpr int kAdjWgPerCu = 2;  // resident adjoint workgroups per CU
+
+Status run_adjoint_fused(StateImpl* s, StateImpl* lam, const std::vector<XGate>& rev,
+                         std::vector<int>* rows, double** slot_sums_dev) {
+  Plan plan;
+  plan_gates(s->n, s->dtype, rev, true, &plan, /*allow_single=*/false, kAdjMaxSlots);
+  const FuseGeom G = fuse_geom(s->dtype);
+  const FOp* dops;
+  const FMapDev* dmaps;
+  Status st = upload_plan(s, plan, G, &dops, &dmaps);
+  if (!st.good()) return st;
+  const uint64_t ntiles = 1ull << (s->n - G.T);
+  const unsigned grid =
+      (unsigned)std::min<uint64_t>(ntiles, (uint64_t)device_cus(s) * kAdjWgPerCu);
+  const size_t nslots = plan.grad_rows.size();
+  // reduction buffer: [slot][grid] partials, then nslots sums
+  st = ensure_dev(s, s->red, (nslots * grid + nslots + 2) * sizeof(double));
+  if (!st.good()) return st;
+  double* part = (double*)s->red.ptr;
+  for (const Pass& p : plan.passes) {
+    const FusedArgs A = pass_args(s, plan, p, G);
+    double* pp = part + (size_t)p.grad_first * grid;
+    if (s->dtype == QS_C128)
+      hipLaunchKernelGGL((k_fused_adj_c128<3>), dim3(grid), dim3(kFuseBlock), 0, s->stream,
+                         (d2*)s->ptr, (d2*)lam->ptr, A, dops + p.op_first, dmaps, pp);
+    else
+      hipLaunchKernelGGL((k_fused_adj_c64<4>), dim3(grid), dim3(kFuseBlock), 0, s->stream,
+                         (f4*)s->ptr, (f4*)lam->ptr, A, dops + p.op_first, dmaps, pp);
+    st = last_launch("fused adjoint pass");
+    if (!st.good()) return st;
+  }
+  double* sums = part + nslots * grid;
+  if (nslots > 0) {
+    st = launch_sum_rows(s, part, (int)nslots, (int)grid, sums);
+    if (!st.good()) return st;
+  }
+  *rows = plan.grad_rows;
+  *slot_sums_dev = sums;
   return Status::ok();
 }
 

@@ -44,7 +44,9 @@ struct StateImpl {
   size_t bytes = 0;
   hipStream_t stream = nullptr;
   int device = 0;
+  int cus = 0;       // compute units of the device (0 = not queried yet)
   DevBuf red;        // reduction partials
+  DevBuf scal;       // small device results (energy)
   DevBuf table;      // uploaded tables
   Staging stage;     // pinned host side of `table`
   double* result_host = nullptr;  // pinned, for reduction results
@@ -137,13 +139,14 @@ struct FOp {
   int32_t kind;
   int32_t tgt;   // kOpU: register bit; kOpDiag: spec of the target; kOpRemap: new FMap index
   int32_t ctl;   // spec of the control (kNoBit when none)
-  int32_t aux;   // kOpRemap: old FMap index; adjoint: gradient slot or -1
+  int32_t aux;   // kOpRemap: old FMap index; adjoint: gradient slot in the pass or -1
   double m[8];   // kOpU: the 2x2; kOpDiag: d0 = (m[0], m[1]), d1 = (m[6], m[7])
 };
 
 enum PassKind { kPassFused = 0, kPass1q = 1, kPassCU = 2 };
 struct Pass {
   int kind;
+  int grad_first, ngrad;  // fused adjoint: rows of this pass's gradient slots in Plan::grad_rows
   int gate;          // streaming passes: index of the gate
   int op_first, nops;  // fused: range in Plan::ops
   int map_load, map_store;
@@ -157,9 +160,25 @@ struct Plan {
   std::vector<FMap> maps;
   std::vector<int> order;  // gate indices in execution order
   std::vector<int> pass_of;  // pass of each gate (by gate index)
+  std::vector<int> grad_rows;  // per fused pass slot: the gate's param (gradient row)
 };
 // Plan `gates` (applied in list order) for an n-qubit state of `dtype`.
-void plan_gates(int n, int dtype, const std::vector<XGate>& gates, bool fuse, Plan* out);
+// allow_single: a pass with one gate may use the streaming kernels.
+// max_grad: at most this many gradient-carrying gates (XGate::param >= 0)
+// per fused pass.
+void plan_gates(int n, int dtype, const std::vector<XGate>& gates, bool fuse, Plan* out,
+                bool allow_single = true, int max_grad = 1 << 30);
+
+// Fused adjoint reverse sweep (n >= tile bits): `rev` holds the daggered
+// gates in reverse order; rotations keep their kind and carry in `param` the
+// index of their gradient row.  On return rows[i] is the gradient row of
+// slot i and slot_sums_dev[i] (device, in the state's reduction buffer) its
+// contribution, summed in a fixed order.
+Status run_adjoint_fused(StateImpl* s, StateImpl* lam, const std::vector<XGate>& rev,
+                         std::vector<int>* rows, double** slot_sums_dev);
+// out[r] = sum of part[r * ncols + c] over c, fixed order (one workgroup per row).
+Status launch_sum_rows(StateImpl* s, const double* part, int nrows, int ncols, double* out);
+constexpr int kAdjMaxSlots = 64;  // gradient rows per fused adjoint pass
 bool gate_is_diagonal(const XGate& g);
 
 // ----------------------------------------------------------- adjoint

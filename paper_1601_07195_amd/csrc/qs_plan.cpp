@@ -3,7 +3,7 @@
 // Cache blocking by gate fusion (qHiPSTER Sec. 4.4, Fig. 4) re-planned for a
 // GPU: instead of one last-level-cache block of the low qubits, every pass
 // picks its own tile -- the low qubits (for coalesced HBM access) plus up to
-// six high qubits -- and takes as many gates as fit, so that the state makes
+// five high qubits -- and takes as many gates as fit, so that the state makes
 // one HBM round trip per pass instead of one per gate.
 //
 // Which gates a pass can take:
@@ -30,12 +30,14 @@ namespace qs {
 
 FuseGeom fuse_geom(int dtype) {
   FuseGeom g;
+  // 8 (complex128) or 16 (complex64) amplitudes per thread: more register
+  // bits raise register pressure past two waves per SIMD on gfx950.
   if (dtype == QS_C128) {
-    g.nreg = 4;
+    g.nreg = 3;
     g.L = 6;
     g.lane0 = 0;
   } else {
-    g.nreg = 5;
+    g.nreg = 4;
     g.L = 7;
     g.lane0 = 1;
   }
@@ -44,6 +46,10 @@ FuseGeom fuse_geom(int dtype) {
 }
 
 bool gate_is_diagonal(const XGate& g) {
+  // A rotation keeps the form of its generator (its gradient term depends
+  // on it): only RZ counts as diagonal, whatever the angle.
+  if (g.kind == QS_OP_RX || g.kind == QS_OP_RY) return false;
+  if (g.kind == QS_OP_RZ) return true;
   return g.m[2] == 0.0 && g.m[3] == 0.0 && g.m[4] == 0.0 && g.m[5] == 0.0;
 }
 
@@ -103,11 +109,13 @@ FMap to_fmap(const Mapping& m) {
 
 }  // namespace
 
-void plan_gates(int n, int dtype, const std::vector<XGate>& gates, bool fuse, Plan* out) {
+void plan_gates(int n, int dtype, const std::vector<XGate>& gates, bool fuse, Plan* out,
+                bool allow_single, int max_grad) {
   out->passes.clear();
   out->ops.clear();
   out->maps.clear();
   out->order.clear();
+  out->grad_rows.clear();
   const int N = (int)gates.size();
   out->pass_of.assign(N, -1);
   const FuseGeom G = fuse_geom(dtype);
@@ -144,8 +152,10 @@ void plan_gates(int n, int dtype, const std::vector<XGate>& gates, bool fuse, Pl
     auto in_tile = [&](int q) {
       return q < G.L || std::find(high.begin(), high.end(), q) != high.end();
     };
+    int ngrad = 0;
     for (int g = start; g < N && g < start + kWindow; ++g) {
       if (done[g]) continue;
+      if (gates[g].param >= 0 && ngrad >= max_grad) break;
       bool blocked = false;
       for (int s : skipped)
         if (!commute(fp[g], fp[s])) {
@@ -156,11 +166,13 @@ void plan_gates(int n, int dtype, const std::vector<XGate>& gates, bool fuse, Pl
         const int t = gates[g].target;
         if (diag[g] || in_tile(t)) {
           take.push_back(g);
+          ngrad += gates[g].param >= 0;
           continue;
         }
         if ((int)high.size() < slots) {
           high.push_back(t);
           take.push_back(g);
+          ngrad += gates[g].param >= 0;
           continue;
         }
       }
@@ -172,7 +184,7 @@ void plan_gates(int n, int dtype, const std::vector<XGate>& gates, bool fuse, Pl
 
     int nondiag = 0;
     for (int g : take) nondiag += !diag[g];
-    if (take.size() == 1) {  // one gate: the streaming kernels are as cheap or cheaper
+    if (take.size() == 1 && allow_single) {  // one gate: the streaming kernels are as cheap or cheaper
       stream_pass(take[0]);
       continue;
     }
@@ -225,6 +237,8 @@ void plan_gates(int n, int dtype, const std::vector<XGate>& gates, bool fuse, Pl
     out->maps.push_back(to_fmap(load));
     p.nh = slots;
     for (int h = 0; h < slots; ++h) p.hpos[h] = (int8_t)high[h];
+    p.grad_first = (int)out->grad_rows.size();
+    p.ngrad = 0;
 
     auto where = [&](const Mapping& m, int q) -> int32_t {
       const int tb = tile_bit_of[q];
@@ -254,8 +268,12 @@ void plan_gates(int n, int dtype, const std::vector<XGate>& gates, bool fuse, Pl
       std::memset(&op, 0, sizeof(op));
       std::memcpy(op.m, x.m, sizeof(op.m));
       op.aux = -1;
+      if (x.param >= 0) {  // gradient slot; the Pauli generator rides in bits 8.. of kind
+        op.aux = p.ngrad++;
+        out->grad_rows.push_back(x.param);
+      }
       if (diag[g]) {
-        op.kind = kOpDiag;
+        op.kind = kOpDiag | (op.aux >= 0 ? (x.kind - QS_OP_RX + 1) << 8 : 0);
         op.tgt = where(cur, x.target);
       } else {
         const int tb = targets[ti];
@@ -297,7 +315,7 @@ void plan_gates(int n, int dtype, const std::vector<XGate>& gates, bool fuse, Pl
           for (int k = 0; k < G.nreg; ++k)
             if (cur.reg[k] == tb) rk = k;
         }
-        op.kind = kOpU;
+        op.kind = kOpU | (op.aux >= 0 ? (x.kind - QS_OP_RX + 1) << 8 : 0);
         op.tgt = rk;
         ++ti;
       }

@@ -99,3 +99,56 @@ def test_state_is_final_flag(Q):
     e, g = Q.grad_adjoint(st, lam, circ.ops, circ.theta, ham.codes, ham.coeff, state_is_final=True)
     rg = O.grad_param_shift(circ.ops, n, circ.theta, ham.codes, ham.coeff)
     assert np.abs(g - rg).max() <= 1e-10
+
+
+@pytest.mark.parametrize("name,n", [("c128", 11), ("c128", 14), ("c64", 12), ("c64", 15)])
+def test_fused_adjoint_vs_parameter_shift(Q, name, n):
+    """States at least one fused tile wide take the fused reverse sweep
+    (psi and lambda in registers, gradients folded per workgroup)."""
+    circ, ham = C.workload_ansatz(n, 2, 25, seed=2000 + n)
+    dtype = Q.QS_C128 if name == "c128" else Q.QS_C64
+    e, g = adjoint(Q, circ, ham, dtype)
+    re = O.energy(circ.ops, n, circ.theta, ham.codes, ham.coeff)
+    sample = list(range(0, circ.nparams, 5))
+    rg = O.grad_param_shift(circ.ops, n, circ.theta, ham.codes, ham.coeff, params=sample)
+    scale = max(1.0, np.abs(ham.coeff).sum())
+    if name == "c128":
+        assert abs(e - re) <= 1e-12
+        assert np.abs(g[sample] - rg[sample]).max() <= 1e-10
+    else:
+        assert abs(e - re) <= 1e-4 * scale
+        assert np.abs(g[sample] - rg[sample]).max() <= 1e-4 * scale
+
+
+def test_fused_adjoint_general_circuit(Q):
+    """Fixed U / CU gates (including diagonal ones and controls on every kind
+    of tile bit) between rotations, RX / RY / RZ, and a shared parameter."""
+    n = 13
+    rng = np.random.default_rng(77)
+    parts = []
+    p = 0
+    for layer in range(3):
+        for q in range(n):
+            kind = [C.OP_RX, C.OP_RY, C.OP_RZ][(q + layer) % 3]
+            parts.append(C.op_rot(kind, q, p % 17))
+            p += 1
+        parts.append(C.random_circuit(n, 12, rng).ops)
+        parts.append(C.op_cu(int(rng.integers(n)), (layer * 5 + 3) % n, np.diag([1, 1j])))
+    ops = np.concatenate(parts)
+    theta = rng.uniform(0, 2 * np.pi, 17)
+    ham = C.random_pauli_sum(n, 20, rng)
+    st = Q.State(n, Q.QS_C128)
+    lam = Q.State(n, Q.QS_C128, init=False)
+    e, g = Q.grad_adjoint(st, lam, ops, theta, ham.codes, ham.coeff)
+    rg = O.grad_param_shift(ops, n, theta, ham.codes, ham.coeff)
+    assert abs(e - O.energy(ops, n, theta, ham.codes, ham.coeff)) <= 1e-12
+    assert np.abs(g - rg).max() <= 1e-10
+    assert np.abs(st.numpy() - O.basis_state(n)).max() <= 1e-12
+
+
+def test_fused_adjoint_reproducible(Q):
+    n = 14
+    circ, ham = C.workload_ansatz(n, 2, 10, seed=9)
+    a = adjoint(Q, circ, ham, Q.QS_C128)
+    b = adjoint(Q, circ, ham, Q.QS_C128)
+    assert a[0] == b[0] and np.array_equal(a[1], b[1])
