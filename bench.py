@@ -48,6 +48,10 @@ def parse():
     ap.add_argument("--ncu", type=int, default=64)
     ap.add_argument("--circuit-gates", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-large", action="store_true", help="skip the n=33/34 (128 GiB) section")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint vs parameter-shift section")
+    ap.add_argument("--ps-pairs", type=int, default=8,
+                    help="parameter-shift pairs timed at n=28 (extrapolated to all 2P sweeps)")
     ap.add_argument("--cpu-n", type=int, default=0, help="qubits of the CPU-oracle sample (0 = auto)")
     return ap.parse_args()
 
@@ -126,6 +130,119 @@ def cpu_baseline(n_gpu: int, u, pairs, args):
         "sample": f"complex128 n={n}: H and Haar U on targets {targets} + 2 controlled-U, "
                   f"{len(gates)} gates, {dt:.2f} s",
     }
+
+
+def timed(fn, stream, reps=1):
+    """Mean seconds of fn() over reps, with HIP events on `stream` after one
+    untimed call."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / reps
+
+
+def large_section(Q, C, np, torch):
+    """The 128 GiB states: n = 33 complex128 and n = 34 complex64.  Per-gate
+    HBM bandwidth on a spread of targets and control/target pairs, then a
+    500-gate random circuit followed by a QFT on all qubits (run fused)."""
+    out = {}
+    stream = torch.cuda.current_stream()
+    for n, name in ((33, "c128"), (34, "c64")):
+        dtype = Q.QS_C128 if name == "c128" else Q.QS_C64
+        S = (1 << n) * (16 if name == "c128" else 8)
+        log(f"[bench] large: n={n} {name} ({S / 2**30:.0f} GiB)")
+        st = Q.State(n, dtype, stream=stream)
+        u, pairs = C.workload_sweep(n, 8, C.SEED_BASE + 2)
+        one = {}
+        for k in (0, 1, 5, 6, 7, 8, 12, 20, 27, n - 1):
+            t = timed(lambda: st.apply_1q(k, u), stream, 3)
+            one[str(k)] = round(2 * S / t / 1e9, 1)
+        cu = {}
+        for c, t_ in [(0, 1), (2, 20), (3, 20), (10, 0), (20, 10), (n - 1, 5)] + pairs[:4]:
+            t = timed(lambda: st.apply_cu(c, t_, u), stream, 3)
+            cu[f"{c},{t_}"] = round(S / t / 1e9, 1)
+        circ = C.workload_circuit_qft(n)
+        info, _, _ = Q.qs_plan(n, dtype, circ.ops)
+        pergate = sum((S if op["kind"] == C.OP_CU else 2 * S) for op in circ.ops)
+        tc = timed(lambda: st.run(circ.ops), stream, 1)
+        out[f"n{n}_{name}"] = {
+            "state_bytes": S,
+            "one_qubit_GBps_by_target": one,
+            "one_qubit_GBps_min": min(one.values()),
+            "cu_alg_GBps": cu,
+            "circuit": {"gates": len(circ), "passes": info["passes"], "s": round(tc, 4),
+                        "hbm_GBps": round(info["hbm_bytes"] / tc / 1e9, 1),
+                        "effective_GBps_paper_def": round(pergate / tc / 1e9, 1),
+                        "paper_qft_only_s": {"33": 245.0, "34": 297.4}[str(n)]},
+        }
+        del st
+        torch.cuda.empty_cache()
+    return out
+
+
+def adjoint_section(Q, C, np, torch, ps_pairs):
+    """Energy + full gradient of the layered ansatz (L = 20, H = 100 Pauli
+    strings) by the adjoint method vs the 2P-sweep parameter-shift rule on the
+    same GPU, FP64 (complex128) state."""
+    out = {}
+    stream = torch.cuda.current_stream()
+    for n in (20, 28):
+        circ, ham = C.workload_ansatz(n, 20, 100)
+        P = circ.nparams
+        x, z = Q.pauli_masks(ham.codes)
+        st = Q.State(n, Q.QS_C128, stream=stream)
+        lam = Q.State(n, Q.QS_C128, stream=stream, init=False)
+        log(f"[bench] adjoint: n={n}, P={P}, gates={len(circ)}")
+
+        def adj():
+            st.init_basis(0)
+            return Q.qs_grad_adjoint(st.handle, circ.ops, circ.theta, x, z, ham.coeff, lam.handle)
+
+        adj()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 3 if n == 20 else 1
+        for _ in range(reps):
+            e, g = adj()
+        t_adj = (time.perf_counter() - t0) / reps
+
+        def energy(th):
+            st.init_basis(0)
+            st.run(circ.ops, th)
+            return Q.qs_expect_pauli(st.handle, x, z, ham.coeff)
+
+        pairs = P if n == 20 else min(ps_pairs, P)
+        energy(circ.theta)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gps = np.zeros(pairs)
+        for j in range(pairs):
+            tp = circ.theta.copy()
+            tm = circ.theta.copy()
+            tp[j] += np.pi / 2
+            tm[j] -= np.pi / 2
+            gps[j] = 0.5 * (energy(tp) - energy(tm))
+        t_pairs = time.perf_counter() - t0
+        t_ps = t_pairs * P / pairs
+        out[f"n{n}"] = {
+            "params": P, "gates": len(circ), "terms": 100,
+            "adjoint_s": round(t_adj, 4), "param_shift_s": round(t_ps, 3),
+            "param_shift_pairs_timed": pairs,
+            "param_shift_extrapolated": pairs < P,
+            "speedup": round(t_ps / t_adj, 1),
+            "max_abs_diff_adjoint_vs_shift": float(np.abs(g[:pairs] - gps).max()),
+            "energy": e,
+        }
+        del st, lam
+        torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -227,6 +344,35 @@ def main():
     copy_gbps = 2 * cs / statistics.median(copy_t) / 1e9
     del src, dst
 
+    # per-kernel rooflines; the dominant kernel (most time in a step) is
+    # reported as `roofline`.  Fused passes: the circuit's event-timed
+    # duration divided by its launches (all fused for this circuit).
+    n_sweep = len(one_q) / args.steps
+    circ_med = statistics.median(circ_t)
+    kernels = {
+        "k_fused (fused pass, circuit)": {
+            "launches_per_step": plan_info["passes"], "bytes_per_launch": 2 * S,
+            "mean_launch_ms": circ_med / plan_info["passes"] * 1e3,
+            "step_s": circ_med},
+        "k_exchange/k_pair (single-qubit gate, streaming)": {
+            "launches_per_step": n_sweep, "bytes_per_launch": 2 * S,
+            "mean_launch_ms": mean_1q * 1e3, "step_s": mean_1q * n_sweep},
+        "k_exchange/k_pair (controlled gate, streaming)": {
+            "launches_per_step": len(pairs), "bytes_per_launch": S,
+            "mean_launch_ms": statistics.fmean(cu_t) * 1e3,
+            "step_s": statistics.fmean(cu_t) * len(pairs)},
+    }
+    for v in kernels.values():
+        v["achieved_GBps"] = round(v["bytes_per_launch"] / (v["mean_launch_ms"] * 1e-3) / 1e9, 1)
+        v["frac"] = round(v["achieved_GBps"] / PEAK_HBM_GBPS, 4)
+        v["mean_launch_ms"] = round(v["mean_launch_ms"], 4)
+        v["step_s"] = round(v["step_s"], 4)
+    dom = max(kernels, key=lambda k: kernels[k]["step_s"])
+    roof = {"kernel": dom, "bound": "hbm", "achieved": kernels[dom]["achieved_GBps"],
+            "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": kernels[dom]["frac"], "traffic": None,
+            "bytes_per_launch": kernels[dom]["bytes_per_launch"],
+            "mean_launch_ms": kernels[dom]["mean_launch_ms"]}
+
     line = {
         "metric": "gate HBM GB/s (% peak) at n=30-34; adjoint grad s vs parameter-shift, same GPU",
         "value": round(value, 1),
@@ -247,12 +393,8 @@ def main():
             "n": n, "state_bytes": S, "parallelism": "single GPU",
         },
         "pct_peak": round(100 * value / PEAK_HBM_GBPS, 1),
-        "roofline": {
-            "kernel": "k_apply_1q (single-qubit gate, streaming)",
-            "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None,
-            "bytes_per_launch": 2 * S, "mean_launch_ms": round(mean_1q * 1e3, 4),
-        },
+        "roofline": roof,
+        "roofline_by_kernel": kernels,
         "detail": {
             "one_qubit_GBps_by_target": {str(k): round(v, 1) for k, v in sorted(tgt_gbps.items())},
             "one_qubit_GBps_min": round(min(tgt_gbps.values()), 1),
@@ -270,10 +412,14 @@ def main():
         "paper_context": "qHiPSTER (Stampede, 1 Xeon E5-2680 socket, complex128, n=29): 1q gate "
                          "0.44 s measured vs 0.43 s bound = 39 GB/s vs STREAM 40 GB/s (Table 2, Sec. 5.4)",
     }
+    del st
+    torch.cuda.empty_cache()
+    if not args.no_large:
+        line["large_states"] = large_section(Q, C, np, torch)
+    if not args.no_adjoint:
+        line["adjoint_vs_param_shift"] = adjoint_section(Q, C, np, torch, args.ps_pairs)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle sample")
-        del st
-        torch.cuda.empty_cache()
         line["cpu_baseline"] = cpu_baseline(n, u, pairs, args)
     print(json.dumps(line), flush=True)
 
