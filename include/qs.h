@@ -222,7 +222,7 @@ typedef struct qs_plan_info {
   int32_t single_1q;    /* single-qubit gates run as their own pass */
   int32_t single_cu;    /* controlled gates run as their own pass */
   int32_t remaps;       /* on-chip register remaps inside fused passes */
-  int32_t reserved;
+  int32_t fused_ops;    /* op records run by fused passes (merged gates + remaps) */
   double hbm_bytes;     /* algorithmic HBM bytes of the whole list */
 } qs_plan_info;
 int qs_plan(int n, int dtype, const qs_op* ops, int nops, const double* theta,

@@ -377,6 +377,7 @@ int qs_plan(int n, int dtype, const qs_op* ops, int nops, const double* theta, i
       if (p.kind == qs::kPassFused) {
         ++info->fused;
         info->remaps += p.remaps;
+        info->fused_ops += p.nops;
         info->hbm_bytes += 2 * S;
       } else if (p.kind == qs::kPass1q) {
         ++info->single_1q;

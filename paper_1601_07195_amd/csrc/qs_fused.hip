@@ -520,7 +520,7 @@ constexpr int kAdjWgPerCu = 2;  // resident adjoint workgroups per CU
 Status run_adjoint_fused(StateImpl* s, StateImpl* lam, const std::vector<XGate>& rev,
                          std::vector<int>* rows, double** slot_sums_dev) {
   Plan plan;
-  plan_gates(s->n, s->dtype, rev, true, &plan, /*allow_single=*/false, kAdjMaxSlots);
+  plan_gates(s->n, s->dtype, rev, true, &plan, /*allow_single=*/false, kAdjMaxSlots, /*grad=*/true);
   const FuseGeom G = fuse_geom(s->dtype);
   const FOp* dops;
   const FMapDev* dmaps;

@@ -166,8 +166,11 @@ struct Plan {
 // allow_single: a pass with one gate may use the streaming kernels.
 // max_grad: at most this many gradient-carrying gates (XGate::param >= 0)
 // per fused pass.
+// grad: gates with param >= 0 get gradient slots (adjoint sweeps) and are
+// never merged with other gates; otherwise consecutive gates on the same
+// target and control may be merged into one op.
 void plan_gates(int n, int dtype, const std::vector<XGate>& gates, bool fuse, Plan* out,
-                bool allow_single = true, int max_grad = 1 << 30);
+                bool allow_single = true, int max_grad = 1 << 30, bool grad = false);
 
 // Fused adjoint reverse sweep (n >= tile bits): `rev` holds the daggered
 // gates in reverse order; rotations keep their kind and carry in `param` the

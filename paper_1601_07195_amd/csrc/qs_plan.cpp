@@ -85,6 +85,32 @@ bool commute(const Footprint& a, const Footprint& b) {
   return true;
 }
 
+// c = a * b for 2x2 complex matrices in the 8-double layout.
+void mul2(const double* a, const double* b, double* c) {
+  double t[8];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      double re = 0.0, im = 0.0;
+      for (int k = 0; k < 2; ++k) {
+        const double ar = a[4 * i + 2 * k], ai = a[4 * i + 2 * k + 1];
+        const double br = b[4 * k + 2 * j], bi = b[4 * k + 2 * j + 1];
+        re += ar * br - ai * bi;
+        im += ar * bi + ai * br;
+      }
+      t[4 * i + 2 * j] = re;
+      t[4 * i + 2 * j + 1] = im;
+    }
+  std::memcpy(c, t, sizeof(t));
+}
+
+// What the planner remembers about an emitted fused op.
+struct OpMeta {
+  bool remap;
+  bool mergeable;  // no gradient slot
+  int target, control;
+  Footprint fp;
+};
+
 // Global qubit held by tile bit tb.
 inline int tile_qubit(int tb, int L, const std::vector<int>& hq) { return tb < L ? tb : hq[tb - L]; }
 
@@ -110,7 +136,7 @@ FMap to_fmap(const Mapping& m) {
 }  // namespace
 
 void plan_gates(int n, int dtype, const std::vector<XGate>& gates, bool fuse, Plan* out,
-                bool allow_single, int max_grad) {
+                bool allow_single, int max_grad, bool grad) {
   out->passes.clear();
   out->ops.clear();
   out->maps.clear();
@@ -142,6 +168,7 @@ void plan_gates(int n, int dtype, const std::vector<XGate>& gates, bool fuse, Pl
     diag[g] = gate_is_diagonal(gates[g]);
   }
   std::vector<char> done(N, 0);
+  std::vector<OpMeta> meta;  // aligned with out->ops
   const int slots = G.T - G.L;
   int start = 0;
   while (start < N) {
@@ -155,7 +182,7 @@ void plan_gates(int n, int dtype, const std::vector<XGate>& gates, bool fuse, Pl
     int ngrad = 0;
     for (int g = start; g < N && g < start + kWindow; ++g) {
       if (done[g]) continue;
-      if (gates[g].param >= 0 && ngrad >= max_grad) break;
+      if (grad && gates[g].param >= 0 && ngrad >= max_grad) break;
       bool blocked = false;
       for (int s : skipped)
         if (!commute(fp[g], fp[s])) {
@@ -166,13 +193,13 @@ void plan_gates(int n, int dtype, const std::vector<XGate>& gates, bool fuse, Pl
         const int t = gates[g].target;
         if (diag[g] || in_tile(t)) {
           take.push_back(g);
-          ngrad += gates[g].param >= 0;
+          ngrad += grad && gates[g].param >= 0;
           continue;
         }
         if ((int)high.size() < slots) {
           high.push_back(t);
           take.push_back(g);
-          ngrad += gates[g].param >= 0;
+          ngrad += grad && gates[g].param >= 0;
           continue;
         }
       }
@@ -258,17 +285,73 @@ void plan_gates(int n, int dtype, const std::vector<XGate>& gates, bool fuse, Pl
       op.tgt = (int)out->maps.size() - 1;
       op.ctl = make_spec(kNoBit, 0);
       out->ops.push_back(op);
+      OpMeta mt;
+      mt.remap = true;
+      mt.mergeable = false;
+      mt.target = mt.control = -1;
+      mt.fp.nq = 0;
+      meta.push_back(mt);
       ++p.remaps;
+    };
+
+    // Fold gate g into the latest earlier op of this pass that it does not
+    // commute with, when both act on the same target and control (the gate
+    // moves back past ops it commutes with, which is exact): U then U, diag
+    // then diag, a diag after a register U, or a U after a diag whose target
+    // sat in a register.  The merged op stays where the earlier one was, with
+    // that op's bit locations.
+    auto try_merge = [&](int g) -> bool {
+      const XGate& x = gates[g];
+      for (int j = (int)out->ops.size() - 1; j >= p.op_first; --j) {
+        OpMeta& m = meta[j];
+        if (m.remap) continue;
+        if (commute(fp[g], m.fp)) continue;
+        if (!m.mergeable || m.target != x.target || m.control != x.control) return false;
+        FOp& y = out->ops[j];
+        const int ykind = y.kind & 255;
+        if (diag[g]) {
+          if (ykind == kOpDiag) {  // elementwise product of diagonals
+            double d0[8] = {x.m[0], x.m[1], 0, 0, 0, 0, 0, 0}, e0[8] = {y.m[0], y.m[1], 0, 0, 0, 0, 0, 0};
+            double d1[8] = {x.m[6], x.m[7], 0, 0, 0, 0, 0, 0}, e1[8] = {y.m[6], y.m[7], 0, 0, 0, 0, 0, 0};
+            double r0[8], r1[8];
+            mul2(d0, e0, r0);
+            mul2(d1, e1, r1);
+            y.m[0] = r0[0]; y.m[1] = r0[1]; y.m[6] = r1[0]; y.m[7] = r1[1];
+          } else {  // diag(x) * U
+            mul2(x.m, y.m, y.m);
+          }
+        } else {
+          if (ykind == kOpU) {
+            mul2(x.m, y.m, y.m);
+          } else {  // U * diag(y): only if y's target was a register bit
+            if ((y.tgt >> 8) != kInReg) return false;
+            double dm[8] = {y.m[0], y.m[1], 0, 0, 0, 0, y.m[6], y.m[7]};
+            mul2(x.m, dm, y.m);
+            y.kind = kOpU;
+            y.tgt = y.tgt & 255;
+          }
+          m.fp.act[0] = 2;  // the merged op is no longer diagonal on its target
+        }
+        return true;
+      }
+      return false;
     };
 
     int ti = 0;  // index into targets
     for (int g : take) {
       const XGate& x = gates[g];
+      const bool gradop = grad && x.param >= 0;
+      if (!gradop && try_merge(g)) {
+        ti += !diag[g];
+        out->pass_of[g] = (int)out->passes.size();
+        out->order.push_back(g);
+        continue;
+      }
       FOp op;
       std::memset(&op, 0, sizeof(op));
       std::memcpy(op.m, x.m, sizeof(op.m));
       op.aux = -1;
-      if (x.param >= 0) {  // gradient slot; the Pauli generator rides in bits 8.. of kind
+      if (gradop) {  // gradient slot; the Pauli generator rides in bits 8.. of kind
         op.aux = p.ngrad++;
         out->grad_rows.push_back(x.param);
       }
@@ -323,6 +406,13 @@ void plan_gates(int n, int dtype, const std::vector<XGate>& gates, bool fuse, Pl
       out->pass_of[g] = (int)out->passes.size();
       out->order.push_back(g);
       out->ops.push_back(op);
+      OpMeta mt;
+      mt.remap = false;
+      mt.mergeable = !gradop;
+      mt.target = x.target;
+      mt.control = x.control;
+      mt.fp = fp[g];
+      meta.push_back(mt);
     }
     // ---- store mapping: coalesced lanes, and (complex64) tile bit 0 in
     // register bit 0; otherwise remap back to the load mapping

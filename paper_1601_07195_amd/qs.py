@@ -63,7 +63,7 @@ _L.qs_stream_copy.argtypes = [_vp, _vp, _sz, _vp]
 class QSPlanInfo(ctypes.Structure):
     _fields_ = [("passes", ctypes.c_int32), ("fused", ctypes.c_int32),
                 ("single_1q", ctypes.c_int32), ("single_cu", ctypes.c_int32),
-                ("remaps", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("remaps", ctypes.c_int32), ("fused_ops", ctypes.c_int32),
                 ("hbm_bytes", ctypes.c_double)]
 
 
@@ -234,7 +234,7 @@ def qs_plan(n: int, dtype: int, ops, theta=None, flags: int = 0):
     pass_of = np.zeros(len(a), dtype=np.int32)
     _check(_L.qs_plan(n, dtype, _ptr(a), len(a), _ptr(th), 0 if th is None else len(th), flags,
                       ctypes.byref(info), _ptr(order), _ptr(pass_of)), "qs_plan")
-    d = {f: getattr(info, f) for f, _ in QSPlanInfo._fields_ if f != "reserved"}
+    d = {f: getattr(info, f) for f, _ in QSPlanInfo._fields_}
     return d, order, pass_of
 
 
