@@ -230,6 +230,68 @@ int qs_plan(int n, int dtype, const qs_op* ops, int nops, const double* theta,
             int32_t* pass_of);
 
 /*
+ * Batched energy and adjoint gradient of many independent small circuits in
+ * one persistent launch.  Batching is not part of the paper; every circuit
+ * computes exactly what qs_grad_adjoint computes for it: the gates of
+ * Eq. (2) / Eq. (3) from |0...0>, E = <psi|H|psi> for its Pauli sum, and
+ * dE/dtheta by one reverse sweep.
+ *
+ * qs_batch_create(dtype, ncircuits, n, op_off, ops, par_off, theta,
+ *                 term_off, x, z, coeff, stream, out)
+ *   Circuit c (0 <= c < ncircuits) has
+ *     n[c] qubits, 1 <= n[c] <= QS_BATCH_MAX_QUBITS;
+ *     gates ops[op_off[c] .. op_off[c+1]) (qs_op records as for qs_run;
+ *       a rotation's param indexes the circuit's own parameters);
+ *     parameters theta[par_off[c] .. par_off[c+1]);
+ *     observable terms x, z, coeff[term_off[c] .. term_off[c+1]) (masks
+ *       below 2^n[c], as for qs_expect_pauli).
+ *   op_off, par_off, term_off: host int64 arrays of ncircuits + 1
+ *   non-decreasing entries starting at 0.  All arrays are host memory and
+ *   are copied: the caller may free them on return.  dtype: QS_C64 or
+ *   QS_C128, the amplitude type of every circuit (energies and gradients
+ *   are accumulated in double precision either way).  stream: the HIP
+ *   stream all later work of the batch is queued on (NULL = default).
+ *   *out receives the handle; the batch owns its device memory (the
+ *   description, a workspace sized at the first run, the outputs).
+ *   Errors: QS_EINVAL (NULL array, bad offsets, an invalid gate, control,
+ *   parameter index or Pauli mask; the message names the circuit),
+ *   QS_ERANGE (n[c] out of range), QS_ENOMEM, QS_ENODEV, QS_EHIP.
+ *
+ * qs_batch_run(b, tuning, energy, grad)
+ *   Runs every circuit once.  energy: host, ncircuits doubles, energy[c] =
+ *   E of circuit c (or NULL).  grad: host, par_off[ncircuits] doubles,
+ *   grad[par_off[c] + p] = dE_c/dtheta_p, summed over the rotations that
+ *   share parameter p (or NULL).  tuning: NULL for the defaults, or the
+ *   launch shape (qs_batch_tuning); results do not depend on it beyond
+ *   floating-point rounding, and for a fixed tuning they are bitwise
+ *   reproducible.  Synchronises the batch's stream before returning.
+ *   Calls on one batch from several host threads race.
+ *   Errors: QS_EINVAL (NULL batch, tuning out of range), QS_ENOMEM
+ *   (workspace), QS_EHIP.
+ *
+ * qs_batch_destroy(b): waits for the batch's stream, frees everything;
+ * NULL is a no-op.
+ */
+#define QS_BATCH_MAX_QUBITS 24
+typedef struct qs_batch qs_batch;
+typedef struct qs_batch_tuning {
+  int32_t threads;     /* threads per workgroup: 256 or 512 (0 = 256) */
+  int32_t lds_bits;    /* C: log2 of the amplitudes per LDS chunk; states of
+                          n <= C qubits stay in LDS, with 2 * 2^C amplitudes
+                          <= 128 KiB (0 = 11) */
+  int32_t khigh;       /* K: chunk qubits above the C - K lowest, chosen per
+                          gate segment: 2 .. min(8, C - 6) (0 = 4) */
+  int32_t wg_per_cu;   /* persistent workgroups per compute unit: 1..8 (0 = 2) */
+  int32_t order;       /* 0 = longest circuit first, 1 = input order */
+} qs_batch_tuning;
+int qs_batch_create(int dtype, int ncircuits, const int32_t* n, const int64_t* op_off,
+                    const qs_op* ops, const int64_t* par_off, const double* theta,
+                    const int64_t* term_off, const uint64_t* x, const uint64_t* z,
+                    const double* coeff, void* stream, qs_batch** out);
+int qs_batch_run(qs_batch* b, const qs_batch_tuning* tuning, double* energy, double* grad);
+int qs_batch_destroy(qs_batch* b);
+
+/*
  * STREAM copy, dst[i] = src[i]: the sustainable-bandwidth probe that the
  * paper's lower bounds are stated against (Sec. 5.2, B_mem "measured by
  * STREAM Copy").  src, dst: device, 16-byte aligned, non-overlapping;

@@ -395,6 +395,53 @@ int qs_plan(int n, int dtype, const qs_op* ops, int nops, const double* theta, i
   return QS_OK;
 }
 
+int qs_batch_create(int dtype, int ncircuits, const int32_t* n, const int64_t* op_off,
+                    const qs_op* ops, const int64_t* par_off, const double* theta,
+                    const int64_t* term_off, const uint64_t* x, const uint64_t* z,
+                    const double* coeff, void* stream, qs_batch** out) {
+  if (!out) return fail(QS_EINVAL, "qs_batch_create: out is NULL");
+  *out = nullptr;
+  if (dtype != QS_C64 && dtype != QS_C128) return fail(QS_EINVAL, "qs_batch_create: bad dtype");
+  if (ncircuits < 0) return fail(QS_EINVAL, "qs_batch_create: ncircuits < 0");
+  if (!op_off || !par_off || !term_off) return fail(QS_EINVAL, "qs_batch_create: NULL offsets");
+  if (op_off[0] != 0 || par_off[0] != 0 || term_off[0] != 0)
+    return fail(QS_EINVAL, "qs_batch_create: offsets must start at 0");
+  for (int c = 0; c < ncircuits; ++c)
+    if (op_off[c + 1] < op_off[c] || par_off[c + 1] < par_off[c] || term_off[c + 1] < term_off[c])
+      return fail(QS_EINVAL, "qs_batch_create: offsets decrease at circuit " + std::to_string(c));
+  if (ncircuits > 0 && !n) return fail(QS_EINVAL, "qs_batch_create: n is NULL");
+  if (op_off[ncircuits] > 0 && !ops) return fail(QS_EINVAL, "qs_batch_create: ops is NULL");
+  if (par_off[ncircuits] > 0 && !theta) return fail(QS_EINVAL, "qs_batch_create: theta is NULL");
+  if (term_off[ncircuits] > 0 && (!x || !z || !coeff))
+    return fail(QS_EINVAL, "qs_batch_create: NULL term array");
+  if (par_off[ncircuits] > INT32_MAX || term_off[ncircuits] > INT32_MAX)
+    return fail(QS_ERANGE, "qs_batch_create: too many parameters or terms");
+  qs::BatchImpl* b = nullptr;
+  Status st = qs::batch_create(dtype, ncircuits, n, op_off, ops, par_off, theta, term_off, x, z,
+                               coeff, (hipStream_t)stream, &b);
+  if (!st.good()) return done(st);
+  qs_batch* h = new (std::nothrow) qs_batch;
+  if (!h) {
+    qs::batch_destroy(b);
+    return fail(QS_ENOMEM, "qs_batch_create: handle allocation failed");
+  }
+  h->impl = b;
+  *out = h;
+  return QS_OK;
+}
+
+int qs_batch_run(qs_batch* b, const qs_batch_tuning* tuning, double* energy, double* grad) {
+  if (!b || !b->impl) return fail(QS_EINVAL, "qs_batch_run: bad batch");
+  return done(qs::batch_run(b->impl, tuning, energy, grad));
+}
+
+int qs_batch_destroy(qs_batch* b) {
+  if (!b) return QS_OK;
+  qs::batch_destroy(b->impl);
+  delete b;
+  return QS_OK;
+}
+
 int qs_stream_copy(const void* src, void* dst, size_t bytes, void* stream) {
   if (!src || !dst) return fail(QS_EINVAL, "qs_stream_copy: NULL pointer");
   if ((((uintptr_t)src) | ((uintptr_t)dst) | bytes) & 15)

@@ -1,0 +1,782 @@
+// qs_batch.hip -- energy and adjoint gradient of many small circuits in one
+// persistent launch.
+//
+// A grid of a few workgroups per CU pulls circuits from an atomic work
+// queue (longest first by default, so the largest circuits do not finish
+// last).  One workgroup runs one circuit at a time, start to end:
+//   1. psi = |0...0>, then the gates in order (Eq. 2 / Eq. 3);
+//   2. lambda = H psi and E = Re <psi|lambda>;
+//   3. the adjoint reverse sweep: for each gate from the last, a rotation
+//      adds Im<lambda|P|psi> to its gradient, then U^dagger goes to psi and
+//      lambda.
+// A state of at most 2^C amplitudes (C = lds_bits) lives in LDS for the
+// whole circuit.  A larger one lives in the workgroup's slot of a global
+// workspace and is processed in segments: a segment is a run of consecutive
+// gates whose qubits all lie in one set of C qubits (the C - K lowest plus K
+// chosen higher ones); the state is gathered 2^C amplitudes at a time into
+// LDS, every gate of the segment is applied there, and the chunk is written
+// back.  This is the paper's cache blocking (Sec. 4.4) with LDS as the
+// cache and a per-segment choice of the blocked qubits.
+//
+// Gradient contributions are double precision: each wavefront reduces its
+// lanes by butterfly and adds the result to its own slot of the rotation's
+// row in the workspace; at the end of the circuit the workgroup adds the
+// wave slots in a fixed order.  Results are bitwise reproducible.
+#include <string.h>
+
+#include <algorithm>
+#include <memory>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "qs_device.h"
+#include "qs_internal.h"
+
+namespace qs {
+
+// Device description of one circuit.
+struct BCirc {
+  int32_t n, nops, nseg, ngroups;
+  int32_t nrot, pad;
+  int64_t op_off, seg_off, grp_off, rot_off;
+};
+// One gate: generator kind, target and control as bit positions inside the
+// gate's segment (the qubit itself when the whole state is in LDS), the
+// matrix index and, for rotations, the rotation's ordinal in its circuit.
+struct BOp {
+  uint8_t kind, lt, lc, pad;  // lc = 0xFF: no control
+  int32_t mat;
+  int32_t rot;                // -1: not a rotation
+  int32_t pad2;
+};
+// Segment: gates [first, first + count); hpos: the K higher qubits (ascending)
+// mapped to chunk bits C - K .. C - 1.
+struct BSeg {
+  int32_t first, count;
+  uint8_t hpos[8];
+};
+
+constexpr int kBatchMaxHigh = 8;
+
+struct BatchDev {
+  const BCirc* circ;
+  const BOp* ops;
+  const BSeg* segs;
+  const double* mats;       // 8 doubles per gate matrix (as applied forward)
+  const PauliGroup* groups;
+  const PauliTerm* terms;   // PauliGroup::first is global into this array
+  const int32_t* order;     // circuit of each queue position
+  double* energy;
+  double* grad_rot;         // one entry per rotation; circuit c's at rot_off
+  unsigned int* counter;
+  char* ws;                 // per-workgroup slots
+  uint64_t ws_slot_bytes;
+  uint64_t state_units;     // amplitudes per state in a slot
+  int32_t ncirc;
+  int32_t lds_bits;         // C
+  int32_t khigh;            // K
+  int32_t pad;
+};
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ uint32_t ins0(uint32_t p, int k) {
+  const uint32_t lo = p & ((1u << k) - 1u);
+  return ((p ^ lo) << 1) | lo;
+}
+// First index of the pair of work item p for a gate on target t (control c
+// or -1): a 0 inserted at t (and at c, whose bit is then set).
+__device__ __forceinline__ uint32_t pair_base32(uint32_t p, int t, int c) {
+  if (c < 0) return ins0(p, t);
+  const int lo = c < t ? c : t, hi = c < t ? t : c;
+  return ins0(ins0(p, lo), hi) | (1u << c);
+}
+
+template <typename R>
+__device__ __forceinline__ void load_mat(const double* m, bool dag, Mat<R>& q) {
+  if (!dag) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      q.r[e] = (R)m[2 * e];
+      q.i[e] = (R)m[2 * e + 1];
+    }
+  } else {  // conjugate transpose
+    q.r[0] = (R)m[0]; q.i[0] = -(R)m[1];
+    q.r[1] = (R)m[4]; q.i[1] = -(R)m[5];
+    q.r[2] = (R)m[2]; q.i[2] = -(R)m[3];
+    q.r[3] = (R)m[6]; q.i[3] = -(R)m[7];
+  }
+}
+
+// q on (t, c) for a 2^m-amplitude array in LDS; V pairs per thread in flight.
+template <typename R, typename T, int B>
+__device__ __forceinline__ void lds_gate(T* a, int m, int t, int c, const Mat<R>& q) {
+  constexpr int V = 2;
+  const uint32_t items = 1u << (m - (c >= 0 ? 2 : 1));
+  const uint32_t s = 1u << t;
+  for (uint32_t p0 = threadIdx.x; p0 < items; p0 += B * V) {
+    T x[V], y[V];
+    uint32_t i0[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      i0[v] = pair_base32(p0 + v * B, t, c);
+      if (p0 + v * B < items) {
+        x[v] = a[i0[v]];
+        y[v] = a[i0[v] + s];
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      if (p0 + v * B < items) {
+        pair_apply(q, x[v], y[v]);
+        a[i0[v]] = x[v];
+        a[i0[v] + s] = y[v];
+      }
+    }
+  }
+}
+
+// Reverse step on (psi, lambda) in LDS: first this thread's share of
+// Im<lambda|P|psi> for generator P (pauli 1..3, 0 = none), then q (the
+// inverse gate) on both arrays.
+template <typename R, typename T, int B>
+__device__ __forceinline__ double lds_gate2(T* a, T* l, int m, int t, int c, const Mat<R>& q,
+                                            int pauli) {
+  const uint32_t items = 1u << (m - (c >= 0 ? 2 : 1));
+  const uint32_t s = 1u << t;
+  double g = 0.0;
+  for (uint32_t p = threadIdx.x; p < items; p += B) {
+    const uint32_t i0 = pair_base32(p, t, c);
+    T x = a[i0], y = a[i0 + s], u = l[i0], w = l[i0 + s];
+    if (pauli) g += pair_grad(pauli, x.x, x.y, y.x, y.y, u.x, u.y, w.x, w.y);
+    pair_apply(q, x, y);
+    pair_apply(q, u, w);
+    a[i0] = x;
+    a[i0 + s] = y;
+    l[i0] = u;
+    l[i0 + s] = w;
+  }
+  return g;
+}
+
+// Global index of chunk element k: low bits of k in place, chunk bits
+// C - K .. C - 1 at hpos, plus the chunk's base.
+__device__ __forceinline__ uint32_t chunk_index(uint32_t k, uint32_t base, int low, int K,
+                                                const int* hp) {
+  uint32_t g = base | (k & ((1u << low) - 1u));
+  const uint32_t kh = k >> low;
+#pragma unroll
+  for (int j = 0; j < kBatchMaxHigh; ++j)
+    if (j < K) g |= ((kh >> j) & 1u) << hp[j];
+  return g;
+}
+// Base index of chunk ch: the bits of ch go, in ascending order, to the
+// qubits >= low that are not among hpos.
+__device__ __forceinline__ uint32_t chunk_base(uint32_t ch, int low, int K, const int* hp) {
+  uint32_t g = ch << low;
+#pragma unroll
+  for (int j = 0; j < kBatchMaxHigh; ++j)
+    if (j < K) g = ins0(g, hp[j]);
+  return g;
+}
+
+template <int B>
+__device__ __forceinline__ double wg_sum(double v, double* red) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int j = 0; j < B / 64; ++j) s += red[j];
+  __syncthreads();
+  return s;
+}
+
+// Dynamic LDS: psi chunk [2^C] then lambda chunk [2^C].
+template <typename R, typename T, int B>
+__global__ void __launch_bounds__(B) k_batch(BatchDev d) {
+  extern __shared__ uint4 lds_raw[];
+  __shared__ int s_idx;
+  __shared__ double red[B / 64];
+  constexpr int NW = B / 64;
+  const int C = d.lds_bits, K = d.khigh, low = C - K;
+  T* lpsi = (T*)lds_raw;
+  T* llam = lpsi + (1u << C);
+  T* wpsi = (T*)(d.ws + (uint64_t)blockIdx.x * d.ws_slot_bytes);
+  T* wlam = wpsi + d.state_units;
+  double* gacc = (double*)(wlam + d.state_units);  // [rotation][wave]
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+
+  for (;;) {
+    if (threadIdx.x == 0) s_idx = (int)atomicAdd(d.counter, 1u);
+    __syncthreads();
+    const int qi = uni(s_idx);
+    __syncthreads();
+    if (qi >= d.ncirc) break;
+    const int ci = uni(d.order[qi]);
+    const BCirc cc = d.circ[ci];
+    const int n = cc.n;
+    const bool whole = n <= C;
+    const int m = whole ? n : C;  // bits of the LDS-resident part
+    const uint32_t nch = whole ? 1u : 1u << (n - C);
+    const uint32_t M = 1u << m;
+    const BOp* ops = d.ops + cc.op_off;
+    const BSeg* segs = d.segs + cc.seg_off;
+
+    // 1. |0...0>, gradient slots cleared, forward sweep
+    T* psi0 = whole ? lpsi : wpsi;
+    for (uint32_t i = threadIdx.x; i < (1u << n); i += B) psi0[i] = make_amp<T>(i == 0 ? 1.0 : 0.0, 0.0);
+    for (int r = threadIdx.x; r < cc.nrot * NW; r += B) gacc[r] = 0.0;
+    __syncthreads();
+    for (int sg = 0; sg < cc.nseg; ++sg) {
+      const BSeg seg = segs[sg];
+      int hp[kBatchMaxHigh];
+#pragma unroll
+      for (int j = 0; j < kBatchMaxHigh; ++j) hp[j] = seg.hpos[j];
+      for (uint32_t ch = 0; ch < nch; ++ch) {
+        const uint32_t base = whole ? 0u : chunk_base(ch, low, K, hp);
+        if (!whole) {
+          for (uint32_t k = threadIdx.x; k < M; k += B) lpsi[k] = wpsi[chunk_index(k, base, low, K, hp)];
+          __syncthreads();
+        }
+        for (int g = seg.first; g < seg.first + seg.count; ++g) {
+          const BOp o = ops[g];
+          Mat<R> q;
+          load_mat<R>(d.mats + (size_t)o.mat * 8, false, q);
+          lds_gate<R, T, B>(lpsi, m, o.lt, o.lc == 0xFF ? -1 : (int)o.lc, q);
+          __syncthreads();
+        }
+        if (!whole) {
+          for (uint32_t k = threadIdx.x; k < M; k += B) wpsi[chunk_index(k, base, low, K, hp)] = lpsi[k];
+          __syncthreads();
+        }
+      }
+    }
+
+    // 2. lambda = H psi (terms grouped by x mask), E = Re<psi|lambda>
+    const T* psi = whole ? lpsi : wpsi;
+    T* lam = whole ? llam : wlam;
+    double e = 0.0;
+    for (uint32_t i = threadIdx.x; i < (1u << n); i += B) {
+      double hr = 0.0, hi = 0.0;
+      for (int g = 0; g < cc.ngroups; ++g) {
+        const PauliGroup G = d.groups[cc.grp_off + g];
+        const uint32_t k = i ^ (uint32_t)G.x;
+        const T b = psi[k];
+        double wr = 0.0, wi = 0.0;
+        for (int j = G.first; j < G.first + G.count; ++j) {
+          const PauliTerm P = d.terms[j];
+          const double sgn = (__popc(k & (uint32_t)P.z) & 1) ? -1.0 : 1.0;
+          wr += sgn * P.cr;
+          wi += sgn * P.ci;
+        }
+        hr += wr * (double)b.x - wi * (double)b.y;
+        hi += wr * (double)b.y + wi * (double)b.x;
+      }
+      lam[i] = make_amp<T>(hr, hi);
+      const T a = psi[i];
+      e += (double)a.x * hr + (double)a.y * hi;
+    }
+    e = wg_sum<B>(e, red);  // its barriers also publish lambda
+
+    // 3. reverse sweep, segments and gates in reverse order
+    for (int sg = cc.nseg - 1; sg >= 0; --sg) {
+      const BSeg seg = segs[sg];
+      int hp[kBatchMaxHigh];
+#pragma unroll
+      for (int j = 0; j < kBatchMaxHigh; ++j) hp[j] = seg.hpos[j];
+      for (uint32_t ch = 0; ch < nch; ++ch) {
+        const uint32_t base = whole ? 0u : chunk_base(ch, low, K, hp);
+        if (!whole) {
+          for (uint32_t k = threadIdx.x; k < M; k += B) {
+            const uint32_t gi = chunk_index(k, base, low, K, hp);
+            lpsi[k] = wpsi[gi];
+            llam[k] = wlam[gi];
+          }
+          __syncthreads();
+        }
+        for (int g = seg.first + seg.count - 1; g >= seg.first; --g) {
+          const BOp o = ops[g];
+          Mat<R> q;
+          load_mat<R>(d.mats + (size_t)o.mat * 8, true, q);
+          const int pauli = o.rot >= 0 ? o.kind - QS_OP_RX + 1 : 0;
+          double gg = lds_gate2<R, T, B>(lpsi, llam, m, o.lt, o.lc == 0xFF ? -1 : (int)o.lc, q,
+                                         pauli);
+          if (o.rot >= 0) {
+            gg = wave_sum(gg);
+            if (lane == 0) gacc[o.rot * NW + wave] += gg;
+          }
+          __syncthreads();
+        }
+        if (!whole) {
+          for (uint32_t k = threadIdx.x; k < M; k += B) {
+            const uint32_t gi = chunk_index(k, base, low, K, hp);
+            wpsi[gi] = lpsi[k];
+            wlam[gi] = llam[k];
+          }
+          __syncthreads();
+        }
+      }
+    }
+
+    // 4. outputs; wave slots added in a fixed order
+    for (int r = threadIdx.x; r < cc.nrot; r += B) {
+      double s = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) s += gacc[r * NW + w];
+      d.grad_rot[cc.rot_off + r] = s;
+    }
+    if (threadIdx.x == 0) d.energy[ci] = e;
+    __syncthreads();
+  }
+}
+
+__global__ void k_batch_reset(unsigned int* counter) {
+  if (threadIdx.x == 0) *counter = 0u;
+}
+
+// ----------------------------------------------------------------- host
+
+namespace {
+
+Status fail_st(int code, const std::string& msg) {
+  Status s;
+  s.code = code;
+  s.msg = msg;
+  return s;
+}
+
+struct HostOp {
+  uint8_t kind;
+  int8_t target, control;  // control -1: none
+  int32_t mat, rot, param;
+};
+
+}  // namespace
+
+struct BatchImpl {
+  int dtype = 0, ncirc = 0, nmax = 0, nrot_max = 0;
+  hipStream_t stream = nullptr;
+  int device = 0, cus = 0;
+  // host description
+  std::vector<int32_t> n;
+  std::vector<int64_t> op_off, par_off, grp_off, rot_off;
+  std::vector<int32_t> ngroups, nrot;
+  std::vector<HostOp> ops;
+  std::vector<double> cost;
+  int64_t nrot_total = 0;
+  // device: static part (matrices, Pauli tables, orders) and outputs
+  void* stat = nullptr;
+  const double* mats_dev = nullptr;
+  const PauliGroup* groups_dev = nullptr;
+  const PauliTerm* terms_dev = nullptr;
+  const int32_t* order_dev = nullptr;  // [LPT order | input order]
+  void* out = nullptr;                 // energy | grad_rot | counter
+  // device: schedule for the current (C, K): circuits, gates, segments
+  void* sched = nullptr;
+  size_t sched_bytes = 0;
+  int sched_C = -1, sched_K = -1;
+  const BCirc* circ_dev = nullptr;
+  const BOp* ops_dev = nullptr;
+  const BSeg* segs_dev = nullptr;
+  int64_t nseg_total = 0;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  double* host_out = nullptr;
+  size_t host_out_bytes = 0;
+};
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Split circuit c into segments for chunk size 2^C with K higher chunk
+// qubits and write its device gates (positions local to their segment).
+void segment_circuit(const BatchImpl& b, int c, int C, int K, std::vector<BOp>& bops,
+                     std::vector<BSeg>& segs) {
+  const int n = b.n[c];
+  const int64_t o0 = b.op_off[c], o1 = b.op_off[c + 1];
+  const int nops = (int)(o1 - o0);
+  const bool whole = n <= C;
+  const int low = C - K;
+  auto emit = [&](int first, int count, std::vector<int>& hs) {
+    BSeg s;
+    memset(&s, 0, sizeof(s));
+    s.first = first;
+    s.count = count;
+    if (!whole) {
+      // fill up to K higher qubits with the lowest unused ones
+      for (int q = low; q < n && (int)hs.size() < K; ++q)
+        if (std::find(hs.begin(), hs.end(), q) == hs.end()) hs.push_back(q);
+      std::sort(hs.begin(), hs.end());
+      for (int j = 0; j < K; ++j) s.hpos[j] = (uint8_t)hs[j];
+    }
+    auto local = [&](int q) -> int {
+      if (whole || q < low) return q;
+      return low + (int)(std::find(hs.begin(), hs.end(), q) - hs.begin());
+    };
+    for (int g = first; g < first + count; ++g) {
+      const HostOp& h = b.ops[o0 + g];
+      BOp& o = bops[bops.size() - nops + g];
+      o.lt = (uint8_t)local(h.target);
+      o.lc = h.control < 0 ? (uint8_t)0xFF : (uint8_t)local(h.control);
+    }
+    segs.push_back(s);
+  };
+  for (int g = 0; g < nops; ++g) {
+    const HostOp& h = b.ops[o0 + g];
+    BOp o;
+    memset(&o, 0, sizeof(o));
+    o.kind = h.kind;
+    o.mat = h.mat;
+    o.rot = h.rot;
+    bops.push_back(o);
+  }
+  if (whole) {
+    std::vector<int> none;
+    emit(0, nops, none);
+    return;
+  }
+  std::vector<int> hs;
+  int first = 0;
+  for (int g = 0; g < nops; ++g) {
+    const HostOp& h = b.ops[o0 + g];
+    int need[2], nn = 0;
+    for (int q : {(int)h.target, (int)h.control})
+      if (q >= low && std::find(hs.begin(), hs.end(), q) == hs.end()) need[nn++] = q;
+    if (nn == 2 && need[0] == need[1]) nn = 1;
+    if ((int)hs.size() + nn > K) {
+      emit(first, g - first, hs);
+      hs.clear();
+      first = g;
+      nn = 0;
+      for (int q : {(int)h.target, (int)h.control})
+        if (q >= low) need[nn++] = q;
+    }
+    for (int j = 0; j < nn; ++j) hs.push_back(need[j]);
+  }
+  if (nops > first) emit(first, nops - first, hs);
+}
+
+}  // namespace
+
+// Build and upload the schedule (circuits, gates, segments) for (C, K).
+static Status build_schedule(BatchImpl* b, int C, int K) {
+  if (b->sched_C == C && b->sched_K == K) return Status::ok();
+  std::vector<BCirc> circ(b->ncirc);
+  std::vector<BOp> bops;
+  std::vector<BSeg> segs;
+  bops.reserve(b->ops.size());
+  for (int c = 0; c < b->ncirc; ++c) {
+    BCirc& cc = circ[c];
+    memset(&cc, 0, sizeof(cc));
+    cc.n = b->n[c];
+    cc.nops = (int32_t)(b->op_off[c + 1] - b->op_off[c]);
+    cc.ngroups = b->ngroups[c];
+    cc.nrot = b->nrot[c];
+    cc.op_off = b->op_off[c];
+    cc.grp_off = b->grp_off[c];
+    cc.rot_off = b->rot_off[c];
+    cc.seg_off = (int64_t)segs.size();
+    segment_circuit(*b, c, C, K, bops, segs);
+    cc.nseg = (int32_t)(segs.size() - cc.seg_off);
+    // every gate position must lie inside the LDS-resident part
+    const int m = std::min(cc.n, C);
+    for (int64_t g = cc.op_off; g < cc.op_off + cc.nops; ++g)
+      if (bops[g].lt >= m || (bops[g].lc != 0xFF && bops[g].lc >= m))
+        return fail_st(QS_EHIP, "batch schedule: gate outside its chunk (internal error)");
+  }
+  const size_t o_circ = 0;
+  const size_t o_ops = align256(o_circ + circ.size() * sizeof(BCirc));
+  const size_t o_segs = align256(o_ops + std::max<size_t>(1, bops.size()) * sizeof(BOp));
+  const size_t total = align256(o_segs + std::max<size_t>(1, segs.size()) * sizeof(BSeg));
+  std::vector<char> blob(total, 0);
+  memcpy(blob.data() + o_circ, circ.data(), circ.size() * sizeof(BCirc));
+  if (!bops.empty()) memcpy(blob.data() + o_ops, bops.data(), bops.size() * sizeof(BOp));
+  memcpy(blob.data() + o_segs, segs.data(), segs.size() * sizeof(BSeg));
+  if (b->sched_bytes < total) {
+    if (b->sched) {
+      Status st = hip_status(hipStreamSynchronize(b->stream), "batch sync");
+      if (!st.good()) return st;
+      (void)hipFree(b->sched);
+    }
+    b->sched = nullptr;
+    b->sched_bytes = 0;
+    b->sched_C = b->sched_K = -1;
+    if (hipMalloc(&b->sched, total) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail_st(QS_ENOMEM, "batch schedule allocation failed");
+    }
+    b->sched_bytes = total;
+  } else {
+    // earlier runs may still read the old schedule
+    Status st = hip_status(hipStreamSynchronize(b->stream), "batch sync");
+    if (!st.good()) return st;
+  }
+  Status st = hip_status(hipMemcpy(b->sched, blob.data(), total, hipMemcpyHostToDevice),
+                         "batch schedule upload");
+  if (!st.good()) return st;
+  char* a = (char*)b->sched;
+  b->circ_dev = (const BCirc*)(a + o_circ);
+  b->ops_dev = (const BOp*)(a + o_ops);
+  b->segs_dev = (const BSeg*)(a + o_segs);
+  b->nseg_total = (int64_t)segs.size();
+  b->sched_C = C;
+  b->sched_K = K;
+  return Status::ok();
+}
+
+Status batch_create(int dtype, int ncirc, const int32_t* n, const int64_t* op_off,
+                    const qs_op* ops, const int64_t* par_off, const double* theta,
+                    const int64_t* term_off, const uint64_t* x, const uint64_t* z,
+                    const double* coeff, hipStream_t stream, BatchImpl** outp) {
+  std::unique_ptr<BatchImpl> b(new (std::nothrow) BatchImpl());
+  if (!b) return fail_st(QS_ENOMEM, "batch handle allocation failed");
+  b->dtype = dtype;
+  b->ncirc = ncirc;
+  b->stream = stream;
+  b->n.assign(n, n + ncirc);
+  b->op_off.assign(op_off, op_off + ncirc + 1);
+  b->par_off.assign(par_off, par_off + ncirc + 1);
+  b->grp_off.resize(ncirc);
+  b->rot_off.resize(ncirc);
+  b->ngroups.resize(ncirc);
+  b->nrot.resize(ncirc);
+  b->ops.reserve((size_t)op_off[ncirc]);
+  std::vector<double> mats;
+  std::unordered_map<std::string, int32_t> fixed_index;  // identical fixed matrices shared
+  std::vector<PauliGroup> groups;
+  std::vector<PauliTerm> terms;
+  std::vector<XGate> gx;
+  int64_t rot_total = 0;
+  for (int c = 0; c < ncirc; ++c) {
+    const std::string who = "qs_batch_create: circuit " + std::to_string(c) + ": ";
+    const int nc = n[c];
+    if (nc < 1 || nc > QS_BATCH_MAX_QUBITS) return fail_st(QS_ERANGE, who + "n out of range");
+    if (op_off[c + 1] < op_off[c] || par_off[c + 1] < par_off[c] || term_off[c + 1] < term_off[c])
+      return fail_st(QS_EINVAL, who + "offsets decrease");
+    if (op_off[c + 1] - op_off[c] > (1 << 30)) return fail_st(QS_ERANGE, who + "too many gates");
+    const int np = (int)(par_off[c + 1] - par_off[c]);
+    Status st = normalize_ops(nc, ops + op_off[c], (int)(op_off[c + 1] - op_off[c]),
+                              np ? theta + par_off[c] : (const double*)nullptr, np, &gx);
+    if (!st.good()) return fail_st(st.code, who + st.msg);
+    b->rot_off[c] = rot_total;
+    int nr = 0;
+    for (const XGate& g : gx) {
+      HostOp h;
+      h.kind = (uint8_t)g.kind;
+      h.target = (int8_t)g.target;
+      h.control = (int8_t)g.control;
+      h.param = g.param;
+      h.rot = g.param >= 0 ? nr++ : -1;
+      if (g.param >= 0) {
+        h.mat = (int32_t)(mats.size() / 8);
+        mats.insert(mats.end(), g.m, g.m + 8);
+      } else {
+        const std::string key((const char*)g.m, sizeof(g.m));
+        auto it = fixed_index.find(key);
+        if (it == fixed_index.end()) {
+          it = fixed_index.emplace(key, (int32_t)(mats.size() / 8)).first;
+          mats.insert(mats.end(), g.m, g.m + 8);
+        }
+        h.mat = it->second;
+      }
+      b->ops.push_back(h);
+    }
+    if (mats.size() / 8 > (size_t)INT32_MAX) return fail_st(QS_ERANGE, who + "too many gates");
+    b->nrot[c] = nr;
+    rot_total += nr;
+    PauliTable t;
+    const int nt = (int)(term_off[c + 1] - term_off[c]);
+    st = build_pauli_table(nc, nt, nt ? x + term_off[c] : nullptr, nt ? z + term_off[c] : nullptr,
+                           nt ? coeff + term_off[c] : nullptr, &t);
+    if (!st.good()) return fail_st(st.code, who + st.msg);
+    b->grp_off[c] = (int64_t)groups.size();
+    b->ngroups[c] = (int32_t)t.groups.size();
+    for (PauliGroup g : t.groups) {
+      g.first += (int32_t)terms.size();
+      groups.push_back(g);
+    }
+    terms.insert(terms.end(), t.terms.begin(), t.terms.end());
+    // work estimate for longest-first ordering: state size x (gates + groups)
+    b->cost.push_back((double)(gx.size() * 3 + t.groups.size() + 1) * (double)(1ull << nc));
+    b->nmax = std::max(b->nmax, nc);
+    b->nrot_max = std::max(b->nrot_max, nr);
+  }
+  b->nrot_total = rot_total;
+  if (hipGetDevice(&b->device) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail_st(QS_ENODEV, "qs_batch_create: no HIP device");
+  }
+  if (hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess ||
+      b->cus <= 0) {
+    (void)hipGetLastError();
+    return fail_st(QS_EHIP, "qs_batch_create: compute unit count unavailable");
+  }
+  // static arena: mats | groups | terms | order (LPT, then input order)
+  const size_t o_mats = 0;
+  const size_t o_groups = align256(o_mats + std::max<size_t>(1, mats.size()) * sizeof(double));
+  const size_t o_terms = align256(o_groups + std::max<size_t>(1, groups.size()) * sizeof(PauliGroup));
+  const size_t o_order = align256(o_terms + std::max<size_t>(1, terms.size()) * sizeof(PauliTerm));
+  const size_t total = align256(o_order + 2 * (size_t)ncirc * sizeof(int32_t));
+  std::vector<char> blob(total, 0);
+  if (!mats.empty()) memcpy(blob.data() + o_mats, mats.data(), mats.size() * sizeof(double));
+  if (!groups.empty()) memcpy(blob.data() + o_groups, groups.data(), groups.size() * sizeof(PauliGroup));
+  if (!terms.empty()) memcpy(blob.data() + o_terms, terms.data(), terms.size() * sizeof(PauliTerm));
+  std::vector<int32_t> ord(2 * (size_t)ncirc);
+  for (int c = 0; c < ncirc; ++c) ord[c] = ord[ncirc + c] = c;
+  std::stable_sort(ord.begin(), ord.begin() + ncirc,
+                   [&](int a, int c) { return b->cost[a] > b->cost[c]; });
+  memcpy(blob.data() + o_order, ord.data(), ord.size() * sizeof(int32_t));
+  if (hipMalloc(&b->stat, total) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail_st(QS_ENOMEM, "qs_batch_create: arena allocation failed");
+  }
+  Status st = hip_status(hipMemcpy(b->stat, blob.data(), total, hipMemcpyHostToDevice), "batch upload");
+  if (!st.good()) {
+    (void)hipFree(b->stat);
+    return st;
+  }
+  char* a = (char*)b->stat;
+  b->mats_dev = (const double*)(a + o_mats);
+  b->groups_dev = (const PauliGroup*)(a + o_groups);
+  b->terms_dev = (const PauliTerm*)(a + o_terms);
+  b->order_dev = (const int32_t*)(a + o_order);
+  const size_t out_bytes = ((size_t)ncirc + (size_t)rot_total + 1) * sizeof(double);
+  if (hipMalloc(&b->out, out_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(b->stat);
+    return fail_st(QS_ENOMEM, "qs_batch_create: output allocation failed");
+  }
+  *outp = b.release();
+  return Status::ok();
+}
+
+void batch_destroy(BatchImpl* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  if (b->stat) (void)hipFree(b->stat);
+  if (b->out) (void)hipFree(b->out);
+  if (b->sched) (void)hipFree(b->sched);
+  if (b->ws) (void)hipFree(b->ws);
+  if (b->host_out) (void)hipHostFree(b->host_out);
+  delete b;
+}
+
+template <typename R, typename T, int B>
+static Status launch_batch(const BatchDev& d, unsigned grid, size_t lds, hipStream_t stream) {
+  auto kern = k_batch<R, T, B>;
+  Status st = hip_status(hipFuncSetAttribute((const void*)kern,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+                         "batch LDS attribute");
+  if (!st.good()) return st;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(B), lds, stream, d);
+  return hip_status(hipGetLastError(), "batch launch");
+}
+
+// Largest workspace the batch may hold (slots of psi, lambda and gradient rows).
+constexpr size_t kBatchWsCap = (size_t)16 << 30;
+
+Status batch_run(BatchImpl* b, const qs_batch_tuning* tune, double* energy, double* grad) {
+  const size_t ab = amp_bytes(b->dtype);
+  int threads = 256, wgcu = 2, order = 0, K = 4;
+  int C = 11;
+  if (tune) {
+    if (tune->threads) threads = tune->threads;
+    if (tune->lds_bits) C = tune->lds_bits;
+    if (tune->wg_per_cu) wgcu = tune->wg_per_cu;
+    if (tune->khigh) K = tune->khigh;
+    order = tune->order;
+  }
+  if (threads != 256 && threads != 512)
+    return fail_st(QS_EINVAL, "qs_batch_run: threads must be 256 or 512");
+  if (C < 8 || C > 13 || (size_t)2 * ((size_t)1 << C) * ab > (size_t)128 * 1024)
+    return fail_st(QS_EINVAL, "qs_batch_run: lds_bits out of range for this dtype");
+  if (K < 2 || K > kBatchMaxHigh || K > C - 6)
+    return fail_st(QS_EINVAL, "qs_batch_run: khigh out of range");
+  if (wgcu < 1 || wgcu > 8) return fail_st(QS_EINVAL, "qs_batch_run: wg_per_cu out of range");
+  if (order != 0 && order != 1) return fail_st(QS_EINVAL, "qs_batch_run: order must be 0 or 1");
+  if (b->ncirc == 0) return Status::ok();
+  Status st = build_schedule(b, C, K);
+  if (!st.good()) return st;
+  const size_t lds = 2 * ((size_t)1 << C) * ab;
+  const int NW = threads / 64;
+  const uint64_t units = b->nmax > C ? 1ull << b->nmax : 0;
+  const size_t slot = align256(2 * units * ab + (size_t)b->nrot_max * NW * sizeof(double));
+  int64_t grid = std::min<int64_t>((int64_t)b->cus * wgcu, b->ncirc);
+  grid = std::max<int64_t>(1, std::min<int64_t>(grid, (int64_t)(kBatchWsCap / std::max<size_t>(slot, 1))));
+  const size_t need = slot * (size_t)grid;
+  if (b->ws_bytes < need) {
+    if (b->ws) {
+      st = hip_status(hipStreamSynchronize(b->stream), "batch sync");
+      if (!st.good()) return st;
+      (void)hipFree(b->ws);
+    }
+    b->ws = nullptr;
+    b->ws_bytes = 0;
+    if (hipMalloc(&b->ws, need) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail_st(QS_ENOMEM, "qs_batch_run: workspace allocation of " + std::to_string(need) +
+                                    " bytes failed");
+    }
+    b->ws_bytes = need;
+  }
+  BatchDev d;
+  memset(&d, 0, sizeof(d));
+  d.circ = b->circ_dev;
+  d.ops = b->ops_dev;
+  d.segs = b->segs_dev;
+  d.mats = b->mats_dev;
+  d.groups = b->groups_dev;
+  d.terms = b->terms_dev;
+  d.order = b->order_dev + (order == 1 ? b->ncirc : 0);
+  d.energy = (double*)b->out;
+  d.grad_rot = d.energy + b->ncirc;
+  d.counter = (unsigned int*)(d.grad_rot + b->nrot_total);
+  d.ws = (char*)b->ws;
+  d.ws_slot_bytes = slot;
+  d.state_units = units;
+  d.ncirc = b->ncirc;
+  d.lds_bits = C;
+  d.khigh = K;
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, b->stream, d.counter);
+  if (b->dtype == QS_C128)
+    st = threads == 256 ? launch_batch<double, d2, 256>(d, (unsigned)grid, lds, b->stream)
+                        : launch_batch<double, d2, 512>(d, (unsigned)grid, lds, b->stream);
+  else
+    st = threads == 256 ? launch_batch<float, f2, 256>(d, (unsigned)grid, lds, b->stream)
+                        : launch_batch<float, f2, 512>(d, (unsigned)grid, lds, b->stream);
+  if (!st.good()) return st;
+  const size_t nout = (size_t)b->ncirc + (size_t)b->nrot_total;
+  if (b->host_out_bytes < nout * sizeof(double)) {
+    if (b->host_out) (void)hipHostFree(b->host_out);
+    b->host_out = nullptr;
+    b->host_out_bytes = 0;
+    if (hipHostMalloc((void**)&b->host_out, nout * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail_st(QS_ENOMEM, "qs_batch_run: pinned host allocation failed");
+    }
+    b->host_out_bytes = nout * sizeof(double);
+  }
+  st = hip_status(hipMemcpyAsync(b->host_out, b->out, nout * sizeof(double), hipMemcpyDeviceToHost,
+                                 b->stream), "batch result copy");
+  if (!st.good()) return st;
+  st = hip_status(hipStreamSynchronize(b->stream), "batch sync");
+  if (!st.good()) return st;
+  if (energy) memcpy(energy, b->host_out, (size_t)b->ncirc * sizeof(double));
+  if (grad) {
+    const int64_t np = b->par_off[b->ncirc];
+    for (int64_t p = 0; p < np; ++p) grad[p] = 0.0;
+    for (int c = 0; c < b->ncirc; ++c)
+      for (int64_t g = b->op_off[c]; g < b->op_off[c + 1]; ++g) {
+        const HostOp& h = b->ops[g];
+        if (h.rot >= 0) grad[b->par_off[c] + h.param] += b->host_out[b->ncirc + b->rot_off[c] + h.rot];
+      }
+  }
+  return Status::ok();
+}
+
+}  // namespace qs

@@ -130,19 +130,20 @@ __device__ __forceinline__ double im_conj_mul(double lr, double li, double wr, d
 }
 
 // Im<lambda|P|psi> restricted to one amplitude pair (target bit 0 / 1),
-// P = X (1), Y (2) or Z (3), in double precision.
+// P = X (1), Y (2) or Z (3), in double precision.  All three are computed
+// and the result is selected: the switch form of this function was lowered
+// incorrectly by the gfx950 backend of this toolchain when inlined into a
+// loop (the Z case read registers of another case), while the select form
+// compiles to straight-line code.
 __device__ __forceinline__ double pair_grad(int pauli, double a0r, double a0i, double a1r,
                                             double a1i, double l0r, double l0i, double l1r,
                                             double l1i) {
-  double w0r, w0i, w1r, w1i;
-  if (pauli == 1) {         // X: (a1, a0)
-    w0r = a1r; w0i = a1i; w1r = a0r; w1i = a0i;
-  } else if (pauli == 2) {  // Y: (-i a1, i a0)
-    w0r = a1i; w0i = -a1r; w1r = -a0i; w1i = a0r;
-  } else {                  // Z: (a0, -a1)
-    w0r = a0r; w0i = a0i; w1r = -a1r; w1i = -a1i;
-  }
-  return im_conj_mul(l0r, l0i, w0r, w0i) + im_conj_mul(l1r, l1i, w1r, w1i);
+  // X psi = (a1, a0); Y psi = (-i a1, i a0); Z psi = (a0, -a1)
+  const double gx = im_conj_mul(l0r, l0i, a1r, a1i) + im_conj_mul(l1r, l1i, a0r, a0i);
+  const double gy = im_conj_mul(l0r, l0i, a1i, -a1r) + im_conj_mul(l1r, l1i, -a0i, a0r);
+  const double gz = im_conj_mul(l0r, l0i, a0r, a0i) + im_conj_mul(l1r, l1i, -a1r, -a1i);
+  const double gxy = pauli == 1 ? gx : gy;
+  return pauli <= 2 ? gxy : gz;
 }
 
 // An amplitude of the storage type from double-precision parts.

@@ -188,8 +188,20 @@ bool gate_is_diagonal(const XGate& g);
 Status run_adjoint(StateImpl* s, StateImpl* lam, const std::vector<XGate>& gates,
                    int nparams, const PauliTable& h, int flags, double* energy, double* grad);
 
+// ------------------------------------------------------------ batches
+struct BatchImpl;
+Status batch_create(int dtype, int ncirc, const int32_t* n, const int64_t* op_off,
+                    const qs_op* ops, const int64_t* par_off, const double* theta,
+                    const int64_t* term_off, const uint64_t* x, const uint64_t* z,
+                    const double* coeff, hipStream_t stream, BatchImpl** out);
+Status batch_run(BatchImpl* b, const qs_batch_tuning* tune, double* energy, double* grad);
+void batch_destroy(BatchImpl* b);
+
 }  // namespace qs
 
 struct qs_state {
   qs::StateImpl impl;
+};
+struct qs_batch {
+  qs::BatchImpl* impl;
 };

@@ -26,6 +26,7 @@ QS_MAX_QUBITS_C128, QS_MAX_QUBITS_C64 = 33, 34
 QS_OP_U, QS_OP_CU, QS_OP_RX, QS_OP_RY, QS_OP_RZ = 0, 1, 2, 3, 4
 QS_RUN_NO_FUSION = 1
 QS_ADJ_STATE_IS_FINAL = 1
+QS_BATCH_MAX_QUBITS = 24
 
 # Mirror of `struct qs_op` (80 bytes).
 QS_OP_DTYPE = np.dtype([("kind", "<i4"), ("target", "<i4"), ("control", "<i4"),
@@ -34,7 +35,8 @@ QS_OP_DTYPE = np.dtype([("kind", "<i4"), ("target", "<i4"), ("control", "<i4"),
 EXPORTED = ("qs_version", "qs_strerror", "qs_last_error", "qs_create", "qs_destroy",
             "qs_set_stream", "qs_init_basis", "qs_apply_1q", "qs_apply_cu", "qs_run",
             "qs_probabilities", "qs_expect_pauli", "qs_apply_pauli_sum", "qs_grad_adjoint",
-            "qs_stream_copy", "qs_plan")
+            "qs_stream_copy", "qs_plan", "qs_batch_create", "qs_batch_run",
+            "qs_batch_destroy")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1601_07195_amd.build`")
@@ -68,6 +70,18 @@ class QSPlanInfo(ctypes.Structure):
 
 
 _L.qs_plan.argtypes = [_i, _i, _vp, _i, _dp, _i, _i, ctypes.POINTER(QSPlanInfo), _vp, _vp]
+
+
+class QSBatchTuning(ctypes.Structure):
+    _fields_ = [("threads", ctypes.c_int32), ("lds_bits", ctypes.c_int32),
+                ("khigh", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
+                ("order", ctypes.c_int32)]
+
+
+_L.qs_batch_create.argtypes = [_i, _i, _vp, _vp, _vp, _vp, _dp, _vp, _vp, _vp, _dp, _vp,
+                               ctypes.POINTER(_vp)]
+_L.qs_batch_run.argtypes = [_vp, ctypes.POINTER(QSBatchTuning), _dp, _dp]
+_L.qs_batch_destroy.argtypes = [_vp]
 for _name in EXPORTED:
     if _name not in ("qs_strerror", "qs_last_error"):
         getattr(_L, _name).restype = _i
@@ -246,6 +260,50 @@ def qs_stream_copy(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
            "qs_stream_copy")
 
 
+def qs_batch_create(dtype: int, n, op_off, ops, par_off, theta, term_off, x, z, coeff,
+                    stream=None) -> int:
+    """Arrays as the C ABI takes them (offsets int64 of ncircuits + 1)."""
+    n = np.ascontiguousarray(n, dtype=np.int32)
+    op_off = np.ascontiguousarray(op_off, dtype=np.int64)
+    par_off = np.ascontiguousarray(par_off, dtype=np.int64)
+    term_off = np.ascontiguousarray(term_off, dtype=np.int64)
+    a = ops_array(ops) if len(ops) else np.zeros(0, dtype=QS_OP_DTYPE)
+    th = _f64(theta)
+    x = np.ascontiguousarray(x, dtype=np.uint64)
+    z = np.ascontiguousarray(z, dtype=np.uint64)
+    c = _f64(coeff)
+    if not (len(op_off) == len(par_off) == len(term_off) == len(n) + 1):
+        raise ValueError("offset arrays need ncircuits + 1 entries")
+    h = _vp()
+    _check(_L.qs_batch_create(dtype, len(n), _ptr(n), _ptr(op_off), _ptr(a), _ptr(par_off),
+                              _ptr(th), _ptr(term_off), _ptr(x), _ptr(z), _ptr(c),
+                              _stream_handle(stream), ctypes.byref(h)), "qs_batch_create")
+    return h.value
+
+
+def _tuning(t) -> QSBatchTuning | None:
+    if t is None:
+        return None
+    if isinstance(t, QSBatchTuning):
+        return t
+    return QSBatchTuning(**{k: int(v) for k, v in dict(t).items() if not k.startswith("_")})
+
+
+def qs_batch_run(h: int, ncircuits: int, nparams: int, tuning=None):
+    """Returns (energy[ncircuits], grad[nparams]) as float64 arrays; tuning
+    is None, a QSBatchTuning or a dict of its fields."""
+    e = np.zeros(ncircuits, dtype=np.float64)
+    g = np.zeros(nparams, dtype=np.float64)
+    t = _tuning(tuning)
+    _check(_L.qs_batch_run(h, None if t is None else ctypes.byref(t), _ptr(e), _ptr(g)),
+           "qs_batch_run")
+    return e, g
+
+
+def qs_batch_destroy(h: int) -> None:
+    _check(_L.qs_batch_destroy(h), "qs_batch_destroy")
+
+
 # ------------------------------------------------------------ conveniences
 
 _TORCH_DTYPE = {QS_C128: torch.complex128, QS_C64: torch.complex64}
@@ -347,3 +405,53 @@ class AdjointEnergy(torch.autograd.Function):
         ctx.saved = None
         gt = torch.from_numpy(g).to(grad_out.device) * grad_out
         return gt, None, None, None, None, None
+
+
+class Batch:
+    """Many independent circuits, each with its own parameters and Pauli-sum
+    observable, run as one persistent launch (qs_batch_*).
+
+    circuits: sequence of (n, ops, theta, codes, coeff); codes (nterms, n)
+    with 0 = I, 1 = X, 2 = Y, 3 = Z.  run() returns (energy[c], [grad_c])."""
+
+    def __init__(self, circuits, dtype: int = QS_C128, stream=None):
+        circuits = list(circuits)
+        self.dtype = dtype
+        self.ncircuits = len(circuits)
+        n = np.array([c[0] for c in circuits], dtype=np.int32)
+        ops = [ops_array(c[1]) for c in circuits]
+        theta = [_f64(c[2]) for c in circuits]
+        masks = [pauli_masks(c[3]) for c in circuits]
+        coeff = [_f64(c[4]) for c in circuits]
+
+        def offsets(parts):
+            o = np.zeros(len(parts) + 1, dtype=np.int64)
+            o[1:] = np.cumsum([len(p) for p in parts])
+            return o
+
+        self.n = n
+        self.op_off, self.par_off, self.term_off = offsets(ops), offsets(theta), offsets(coeff)
+        cat = lambda parts, dt: np.concatenate(parts) if parts else np.zeros(0, dtype=dt)
+        self.handle = qs_batch_create(
+            dtype, n, self.op_off, cat(ops, QS_OP_DTYPE), self.par_off, cat(theta, np.float64),
+            self.term_off, cat([m[0] for m in masks], np.uint64),
+            cat([m[1] for m in masks], np.uint64), cat(coeff, np.float64), stream)
+
+    def run_flat(self, tuning=None):
+        """(energy[ncircuits], concatenated gradient) from one launch."""
+        return qs_batch_run(self.handle, self.ncircuits, int(self.par_off[-1]), tuning)
+
+    def run(self, tuning=None):
+        e, g = self.run_flat(tuning)
+        return e, [g[self.par_off[c]:self.par_off[c + 1]] for c in range(self.ncircuits)]
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            qs_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
