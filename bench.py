@@ -20,7 +20,10 @@ per-gate byte counts (qHiPSTER Table 2: 2 * 2^n * b for a single-qubit gate,
 Extra objects on the same JSON line: `roofline` for the dominant kernel
 (timed with HIP events on the stream the kernels run on), `cpu_baseline`
 (the CPU oracle on a bounded sample), `stream_copy` (measured B_mem) and
-per-category detail.  One GPU only: --gpus above 1 exits with a message.
+per-category detail.  Further sections (each skippable): n=33 / n=34 large
+states, adjoint vs parameter-shift gradients (n=20, n=28), and the batched
+persistent launch (4096 small ansatz circuits, energy + gradient).  One GPU
+only: --gpus above 1 exits with a message.
 """
 from __future__ import annotations
 
@@ -50,6 +53,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip the n=33/34 (128 GiB) section")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint vs parameter-shift section")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-launch section")
     ap.add_argument("--ps-pairs", type=int, default=8,
                     help="parameter-shift pairs timed at n=28 (extrapolated to all 2P sweeps)")
     ap.add_argument("--cpu-n", type=int, default=0, help="qubits of the CPU-oracle sample (0 = auto)")
@@ -245,6 +249,71 @@ def adjoint_section(Q, C, np, torch, ps_pairs):
     return out
 
 
+def batch_section(Q, C, np, torch):
+    """4096 independent ansatz circuits (n uniform in 10..18, L in 5..30, 20
+    Pauli strings each): energy + full adjoint gradient of all of them in one
+    persistent launch (qs_batch_run), complex128 and complex64, with the
+    launch shape chosen by the autotuner on a quarter of the batch.  Compared
+    with one qs_grad_adjoint call per circuit on the same GPU (timed on every
+    64th circuit, extrapolated)."""
+    from paper_1601_07195_amd import autotune as A
+    wl = C.workload_batch(4096)
+    items = [(c.n, c.ops, c.theta, h.codes, h.coeff) for c, h in wl]
+    nparams = sum(len(i[2]) for i in items)
+    # LDS traffic model of the kernel: every gate reads and writes each
+    # amplitude of psi once forward and of psi and lambda once in reverse
+    upd = sum(len(i[1]) * (1 << i[0]) * 3 for i in items)
+    out = {"circuits": len(items), "gates": sum(len(i[1]) for i in items), "params": nparams}
+    ref = None
+    for dt, name, ab in ((Q.QS_C128, "c128", 16), (Q.QS_C64, "c64", 8)):
+        t0 = time.perf_counter()
+        b = Q.Batch(items, dt)
+        t_create = time.perf_counter() - t0
+        sample = Q.Batch(items[::4], dt)
+        tune = A.tune(sample, repeats=1)
+        sample.close()
+        shape = A.fields(tune)
+        log(f"[bench] batch {name}: tuned {shape}")
+        b.run_flat(shape)
+        b.run_flat(A.DEFAULT)
+        times, times_def = [], []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            e, g = b.run_flat(shape)
+            times.append(time.perf_counter() - t0)
+            t0 = time.perf_counter()
+            b.run_flat(A.DEFAULT)
+            times_def.append(time.perf_counter() - t0)
+        t_b = statistics.median(times)
+        idx = list(range(0, len(items), 64))
+        t0 = time.perf_counter()
+        for i in idx:
+            n, ops, th, codes, coeff = items[i]
+            st = Q.State(n, dt)
+            lam = Q.State(n, dt, init=False)
+            Q.grad_adjoint(st, lam, ops, th, codes, coeff)
+        torch.cuda.synchronize()
+        t_un = (time.perf_counter() - t0) * len(items) / len(idx)
+        rec = {
+            "create_s": round(t_create, 3), "tuning": shape,
+            "batch_s": round(t_b, 4), "batch_default_shape_s": round(statistics.median(times_def), 4),
+            "circuits_per_s": round(len(items) / t_b, 1),
+            "gradient_entries_per_s": round(nparams / t_b, 1),
+            "unbatched_s_extrapolated": round(t_un, 3), "unbatched_circuits_timed": len(idx),
+            "speedup_vs_unbatched": round(t_un / t_b, 1),
+            "lds_bytes_model": upd * 2 * ab,
+            "lds_GBps_model": round(upd * 2 * ab / t_b / 1e9, 1),
+        }
+        if ref is None:
+            ref = (e, g)
+        else:
+            rec["max_abs_diff_vs_c128"] = {"energy": float(np.abs(e - ref[0]).max()),
+                                           "gradient": float(np.abs(g - ref[1]).max())}
+        out[name] = rec
+        b.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -418,6 +487,8 @@ def main():
         line["large_states"] = large_section(Q, C, np, torch)
     if not args.no_adjoint:
         line["adjoint_vs_param_shift"] = adjoint_section(Q, C, np, torch, args.ps_pairs)
+    if not args.no_batch:
+        line["batch"] = batch_section(Q, C, np, torch)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle sample")
         line["cpu_baseline"] = cpu_baseline(n, u, pairs, args)

@@ -4,19 +4,26 @@
 // A grid of a few workgroups per CU pulls circuits from an atomic work
 // queue (longest first by default, so the largest circuits do not finish
 // last).  One workgroup runs one circuit at a time, start to end:
-//   1. psi = |0...0>, then the gates in order (Eq. 2 / Eq. 3);
+//   1. psi = |0...0>, then the gates (Eq. 2 / Eq. 3);
 //   2. lambda = H psi and E = Re <psi|lambda>;
 //   3. the adjoint reverse sweep: for each gate from the last, a rotation
 //      adds Im<lambda|P|psi> to its gradient, then U^dagger goes to psi and
 //      lambda.
 // A state of at most 2^C amplitudes (C = lds_bits) lives in LDS for the
 // whole circuit.  A larger one lives in the workgroup's slot of a global
-// workspace and is processed in segments: a segment is a run of consecutive
-// gates whose qubits all lie in one set of C qubits (the C - K lowest plus K
-// chosen higher ones); the state is gathered 2^C amplitudes at a time into
-// LDS, every gate of the segment is applied there, and the chunk is written
+// workspace and is processed in segments: a segment is a set of gates whose
+// qubits all lie in one set of C qubits (the C - K lowest plus K chosen
+// higher ones); the state is gathered 2^C amplitudes at a time into LDS,
+// every gate of the segment is applied there, and the chunk is written
 // back.  This is the paper's cache blocking (Sec. 4.4) with LDS as the
-// cache and a per-segment choice of the blocked qubits.
+// cache and a per-segment choice of the blocked qubits.  The host builds the
+// segments greedily and may move a gate ahead of earlier gates it commutes
+// with (every shared qubit acted on diagonally by both), which changes
+// neither the state nor, since commuting rotations keep their own
+// generator, the gradient.
+//
+// Gate records (kind, positions, matrix) of each block of up to kRecBlock
+// gates are staged in LDS before use, so a gate costs LDS reads only.
 //
 // Gradient contributions are double precision: each wavefront reduces its
 // lanes by butterfly and adds the result to its own slot of the rotation's
@@ -40,31 +47,33 @@ namespace qs {
 struct BCirc {
   int32_t n, nops, nseg, ngroups;
   int32_t nrot, pad;
-  int64_t op_off, seg_off, grp_off, rot_off;
+  int64_t rec_off, seg_off, grp_off, rot_off;
 };
-// One gate: generator kind, target and control as bit positions inside the
-// gate's segment (the qubit itself when the whole state is in LDS), the
-// matrix index and, for rotations, the rotation's ordinal in its circuit.
-struct BOp {
+// One gate in execution order: generator kind, target and control as bit
+// positions inside the gate's segment (the qubit itself when the whole
+// state is in LDS), the rotation's ordinal in its circuit (-1: not a
+// rotation) and the matrix applied in the forward sweep.
+struct BRec {
   uint8_t kind, lt, lc, pad;  // lc = 0xFF: no control
-  int32_t mat;
-  int32_t rot;                // -1: not a rotation
-  int32_t pad2;
+  int32_t rot;
+  int32_t pad2[2];
+  double m[8];
 };
-// Segment: gates [first, first + count); hpos: the K higher qubits (ascending)
-// mapped to chunk bits C - K .. C - 1.
+static_assert(sizeof(BRec) == 80, "gate record layout");
+// Segment: records [first, first + count) of its circuit; hpos: the K
+// higher qubits (ascending) held by chunk bits C - K .. C - 1.
 struct BSeg {
   int32_t first, count;
   uint8_t hpos[8];
 };
 
 constexpr int kBatchMaxHigh = 8;
+constexpr int kRecBlock = 64;  // gate records staged in LDS at a time
 
 struct BatchDev {
   const BCirc* circ;
-  const BOp* ops;
+  const BRec* recs;
   const BSeg* segs;
-  const double* mats;       // 8 doubles per gate matrix (as applied forward)
   const PauliGroup* groups;
   const PauliTerm* terms;   // PauliGroup::first is global into this array
   const int32_t* order;     // circuit of each queue position
@@ -94,19 +103,20 @@ __device__ __forceinline__ uint32_t pair_base32(uint32_t p, int t, int c) {
   return ins0(ins0(p, lo), hi) | (1u << c);
 }
 
+// The record's matrix, or its conjugate transpose, in compute precision.
 template <typename R>
-__device__ __forceinline__ void load_mat(const double* m, bool dag, Mat<R>& q) {
+__device__ __forceinline__ void rec_mat(const BRec& r, bool dag, Mat<R>& q) {
   if (!dag) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      q.r[e] = (R)m[2 * e];
-      q.i[e] = (R)m[2 * e + 1];
+      q.r[e] = (R)r.m[2 * e];
+      q.i[e] = (R)r.m[2 * e + 1];
     }
-  } else {  // conjugate transpose
-    q.r[0] = (R)m[0]; q.i[0] = -(R)m[1];
-    q.r[1] = (R)m[4]; q.i[1] = -(R)m[5];
-    q.r[2] = (R)m[2]; q.i[2] = -(R)m[3];
-    q.r[3] = (R)m[6]; q.i[3] = -(R)m[7];
+  } else {
+    q.r[0] = (R)r.m[0]; q.i[0] = -(R)r.m[1];
+    q.r[1] = (R)r.m[4]; q.i[1] = -(R)r.m[5];
+    q.r[2] = (R)r.m[2]; q.i[2] = -(R)r.m[3];
+    q.r[3] = (R)r.m[6]; q.i[3] = -(R)r.m[7];
   }
 }
 
@@ -144,19 +154,36 @@ __device__ __forceinline__ void lds_gate(T* a, int m, int t, int c, const Mat<R>
 template <typename R, typename T, int B>
 __device__ __forceinline__ double lds_gate2(T* a, T* l, int m, int t, int c, const Mat<R>& q,
                                             int pauli) {
+  constexpr int V = 2;
   const uint32_t items = 1u << (m - (c >= 0 ? 2 : 1));
   const uint32_t s = 1u << t;
   double g = 0.0;
-  for (uint32_t p = threadIdx.x; p < items; p += B) {
-    const uint32_t i0 = pair_base32(p, t, c);
-    T x = a[i0], y = a[i0 + s], u = l[i0], w = l[i0 + s];
-    if (pauli) g += pair_grad(pauli, x.x, x.y, y.x, y.y, u.x, u.y, w.x, w.y);
-    pair_apply(q, x, y);
-    pair_apply(q, u, w);
-    a[i0] = x;
-    a[i0 + s] = y;
-    l[i0] = u;
-    l[i0 + s] = w;
+  for (uint32_t p0 = threadIdx.x; p0 < items; p0 += B * V) {
+    T x[V], y[V], u[V], w[V];
+    uint32_t i0[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      i0[v] = pair_base32(p0 + v * B, t, c);
+      if (p0 + v * B < items) {
+        x[v] = a[i0[v]];
+        y[v] = a[i0[v] + s];
+        u[v] = l[i0[v]];
+        w[v] = l[i0[v] + s];
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      if (p0 + v * B < items) {
+        if (pauli)
+          g += pair_grad(pauli, x[v].x, x[v].y, y[v].x, y[v].y, u[v].x, u[v].y, w[v].x, w[v].y);
+        pair_apply(q, x[v], y[v]);
+        pair_apply(q, u[v], w[v]);
+        a[i0[v]] = x[v];
+        a[i0[v] + s] = y[v];
+        l[i0[v]] = u[v];
+        l[i0[v] + s] = w[v];
+      }
+    }
   }
   return g;
 }
@@ -195,7 +222,51 @@ __device__ __forceinline__ double wg_sum(double v, double* red) {
   return s;
 }
 
-// Dynamic LDS: psi chunk [2^C] then lambda chunk [2^C].
+// Copy `count` (<= kRecBlock) records into LDS.
+template <int B>
+__device__ __forceinline__ void stage_recs(BRec* dst, const BRec* src, int count) {
+  constexpr int W = sizeof(BRec) / 16;
+  const uint4* s = (const uint4*)src;
+  uint4* t = (uint4*)dst;
+  for (int k = threadIdx.x; k < count * W; k += B) t[k] = s[k];
+}
+
+// psi = |0...0> over 2^n amplitudes.
+template <typename T, int B>
+__device__ __forceinline__ void init_zero_state(T* psi, int n) {
+  for (uint32_t i = threadIdx.x; i < (1u << n); i += B) psi[i] = make_amp<T>(i == 0 ? 1.0 : 0.0, 0.0);
+}
+
+// lambda = H psi over 2^n amplitudes (terms grouped by x mask); returns this
+// thread's part of Re<psi|lambda>.
+template <typename T, int B>
+__device__ __forceinline__ double apply_h(const T* psi, T* lam, int n, const PauliGroup* groups,
+                                          int ngroups, const PauliTerm* terms) {
+  double e = 0.0;
+  for (uint32_t i = threadIdx.x; i < (1u << n); i += B) {
+    double hr = 0.0, hi = 0.0;
+    for (int g = 0; g < ngroups; ++g) {
+      const PauliGroup G = groups[g];
+      const uint32_t k = i ^ (uint32_t)G.x;
+      const T b = psi[k];
+      double wr = 0.0, wi = 0.0;
+      for (int j = G.first; j < G.first + G.count; ++j) {
+        const PauliTerm P = terms[j];
+        const double sgn = (__popc(k & (uint32_t)P.z) & 1) ? -1.0 : 1.0;
+        wr += sgn * P.cr;
+        wi += sgn * P.ci;
+      }
+      hr += wr * (double)b.x - wi * (double)b.y;
+      hi += wr * (double)b.y + wi * (double)b.x;
+    }
+    lam[i] = make_amp<T>(hr, hi);
+    const T a = psi[i];
+    e += (double)a.x * hr + (double)a.y * hi;
+  }
+  return e;
+}
+
+// Dynamic LDS: psi chunk [2^C], lambda chunk [2^C], gate records [kRecBlock].
 template <typename R, typename T, int B>
 __global__ void __launch_bounds__(B) k_batch(BatchDev d) {
   extern __shared__ uint4 lds_raw[];
@@ -205,6 +276,7 @@ __global__ void __launch_bounds__(B) k_batch(BatchDev d) {
   const int C = d.lds_bits, K = d.khigh, low = C - K;
   T* lpsi = (T*)lds_raw;
   T* llam = lpsi + (1u << C);
+  BRec* lrec = (BRec*)(llam + (1u << C));
   T* wpsi = (T*)(d.ws + (uint64_t)blockIdx.x * d.ws_slot_bytes);
   T* wlam = wpsi + d.state_units;
   double* gacc = (double*)(wlam + d.state_units);  // [rotation][wave]
@@ -223,12 +295,12 @@ __global__ void __launch_bounds__(B) k_batch(BatchDev d) {
     const int m = whole ? n : C;  // bits of the LDS-resident part
     const uint32_t nch = whole ? 1u : 1u << (n - C);
     const uint32_t M = 1u << m;
-    const BOp* ops = d.ops + cc.op_off;
+    const BRec* recs = d.recs + cc.rec_off;
     const BSeg* segs = d.segs + cc.seg_off;
 
     // 1. |0...0>, gradient slots cleared, forward sweep
-    T* psi0 = whole ? lpsi : wpsi;
-    for (uint32_t i = threadIdx.x; i < (1u << n); i += B) psi0[i] = make_amp<T>(i == 0 ? 1.0 : 0.0, 0.0);
+    if (whole) init_zero_state<T, B>(lpsi, n);
+    else init_zero_state<T, B>(wpsi, n);
     for (int r = threadIdx.x; r < cc.nrot * NW; r += B) gacc[r] = 0.0;
     __syncthreads();
     for (int sg = 0; sg < cc.nseg; ++sg) {
@@ -240,14 +312,19 @@ __global__ void __launch_bounds__(B) k_batch(BatchDev d) {
         const uint32_t base = whole ? 0u : chunk_base(ch, low, K, hp);
         if (!whole) {
           for (uint32_t k = threadIdx.x; k < M; k += B) lpsi[k] = wpsi[chunk_index(k, base, low, K, hp)];
-          __syncthreads();
         }
-        for (int g = seg.first; g < seg.first + seg.count; ++g) {
-          const BOp o = ops[g];
-          Mat<R> q;
-          load_mat<R>(d.mats + (size_t)o.mat * 8, false, q);
-          lds_gate<R, T, B>(lpsi, m, o.lt, o.lc == 0xFF ? -1 : (int)o.lc, q);
+        for (int b0 = 0; b0 < seg.count; b0 += kRecBlock) {
+          const int nb = min(kRecBlock, seg.count - b0);
+          stage_recs<B>(lrec, recs + seg.first + b0, nb);
           __syncthreads();
+          for (int j = 0; j < nb; ++j) {
+            const int hdr = uni(*(const int*)&lrec[j]);
+            const int lt = (hdr >> 8) & 0xFF, lc8 = (hdr >> 16) & 0xFF;
+            Mat<R> q;
+            rec_mat<R>(lrec[j], false, q);
+            lds_gate<R, T, B>(lpsi, m, lt, lc8 == 0xFF ? -1 : lc8, q);
+            __syncthreads();
+          }
         }
         if (!whole) {
           for (uint32_t k = threadIdx.x; k < M; k += B) wpsi[chunk_index(k, base, low, K, hp)] = lpsi[k];
@@ -256,30 +333,12 @@ __global__ void __launch_bounds__(B) k_batch(BatchDev d) {
       }
     }
 
-    // 2. lambda = H psi (terms grouped by x mask), E = Re<psi|lambda>
-    const T* psi = whole ? lpsi : wpsi;
-    T* lam = whole ? llam : wlam;
-    double e = 0.0;
-    for (uint32_t i = threadIdx.x; i < (1u << n); i += B) {
-      double hr = 0.0, hi = 0.0;
-      for (int g = 0; g < cc.ngroups; ++g) {
-        const PauliGroup G = d.groups[cc.grp_off + g];
-        const uint32_t k = i ^ (uint32_t)G.x;
-        const T b = psi[k];
-        double wr = 0.0, wi = 0.0;
-        for (int j = G.first; j < G.first + G.count; ++j) {
-          const PauliTerm P = d.terms[j];
-          const double sgn = (__popc(k & (uint32_t)P.z) & 1) ? -1.0 : 1.0;
-          wr += sgn * P.cr;
-          wi += sgn * P.ci;
-        }
-        hr += wr * (double)b.x - wi * (double)b.y;
-        hi += wr * (double)b.y + wi * (double)b.x;
-      }
-      lam[i] = make_amp<T>(hr, hi);
-      const T a = psi[i];
-      e += (double)a.x * hr + (double)a.y * hi;
-    }
+    // 2. lambda = H psi, E = Re<psi|lambda>
+    double e;
+    if (whole)
+      e = apply_h<T, B>(lpsi, llam, n, d.groups + cc.grp_off, cc.ngroups, d.terms);
+    else
+      e = apply_h<T, B>(wpsi, wlam, n, d.groups + cc.grp_off, cc.ngroups, d.terms);
     e = wg_sum<B>(e, red);  // its barriers also publish lambda
 
     // 3. reverse sweep, segments and gates in reverse order
@@ -296,20 +355,25 @@ __global__ void __launch_bounds__(B) k_batch(BatchDev d) {
             lpsi[k] = wpsi[gi];
             llam[k] = wlam[gi];
           }
-          __syncthreads();
         }
-        for (int g = seg.first + seg.count - 1; g >= seg.first; --g) {
-          const BOp o = ops[g];
-          Mat<R> q;
-          load_mat<R>(d.mats + (size_t)o.mat * 8, true, q);
-          const int pauli = o.rot >= 0 ? o.kind - QS_OP_RX + 1 : 0;
-          double gg = lds_gate2<R, T, B>(lpsi, llam, m, o.lt, o.lc == 0xFF ? -1 : (int)o.lc, q,
-                                         pauli);
-          if (o.rot >= 0) {
-            gg = wave_sum(gg);
-            if (lane == 0) gacc[o.rot * NW + wave] += gg;
-          }
+        for (int b1 = seg.count; b1 > 0; b1 -= kRecBlock) {
+          const int b0 = max(0, b1 - kRecBlock), nb = b1 - b0;
+          stage_recs<B>(lrec, recs + seg.first + b0, nb);
           __syncthreads();
+          for (int j = nb - 1; j >= 0; --j) {
+            const int hdr = uni(*(const int*)&lrec[j]);
+            const int kind = hdr & 0xFF, lt = (hdr >> 8) & 0xFF, lc8 = (hdr >> 16) & 0xFF;
+            const int rot = uni(lrec[j].rot);
+            Mat<R> q;
+            rec_mat<R>(lrec[j], true, q);
+            const int pauli = rot >= 0 ? kind - QS_OP_RX + 1 : 0;
+            double gg = lds_gate2<R, T, B>(lpsi, llam, m, lt, lc8 == 0xFF ? -1 : lc8, q, pauli);
+            if (rot >= 0) {
+              gg = wave_sum(gg);
+              if (lane == 0) gacc[rot * NW + wave] += gg;
+            }
+            __syncthreads();
+          }
         }
         if (!whole) {
           for (uint32_t k = threadIdx.x; k < M; k += B) {
@@ -352,6 +416,8 @@ Status fail_st(int code, const std::string& msg) {
 struct HostOp {
   uint8_t kind;
   int8_t target, control;  // control -1: none
+  uint32_t qmask;          // qubits acted on
+  uint32_t dmask;          // qubits acted on diagonally (a control; a diagonal target)
   int32_t mat, rot, param;
 };
 
@@ -366,21 +432,21 @@ struct BatchImpl {
   std::vector<int64_t> op_off, par_off, grp_off, rot_off;
   std::vector<int32_t> ngroups, nrot;
   std::vector<HostOp> ops;
+  std::vector<double> mats;  // 8 doubles per matrix (fixed matrices shared)
   std::vector<double> cost;
   int64_t nrot_total = 0;
-  // device: static part (matrices, Pauli tables, orders) and outputs
+  // device: static part (Pauli tables, orders) and outputs
   void* stat = nullptr;
-  const double* mats_dev = nullptr;
   const PauliGroup* groups_dev = nullptr;
   const PauliTerm* terms_dev = nullptr;
   const int32_t* order_dev = nullptr;  // [LPT order | input order]
   void* out = nullptr;                 // energy | grad_rot | counter
-  // device: schedule for the current (C, K): circuits, gates, segments
+  // device: schedule for the current (C, K): circuits, gate records, segments
   void* sched = nullptr;
   size_t sched_bytes = 0;
   int sched_C = -1, sched_K = -1;
   const BCirc* circ_dev = nullptr;
-  const BOp* ops_dev = nullptr;
+  const BRec* recs_dev = nullptr;
   const BSeg* segs_dev = nullptr;
   int64_t nseg_total = 0;
   void* ws = nullptr;
@@ -393,22 +459,28 @@ namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// Scan limits of the segment builder: gates looked at past the first
+// unplaced one, and gates left behind, per segment.
+constexpr int kSegWindow = 512;
+constexpr int kSegSkip = 96;
+
 // Split circuit c into segments for chunk size 2^C with K higher chunk
-// qubits and write its device gates (positions local to their segment).
-void segment_circuit(const BatchImpl& b, int c, int C, int K, std::vector<BOp>& bops,
+// qubits; append its gate records (execution order, positions local to
+// their segment) and its segments (first = index into `recs`).
+void segment_circuit(const BatchImpl& b, int c, int C, int K, std::vector<BRec>& recs,
                      std::vector<BSeg>& segs) {
   const int n = b.n[c];
-  const int64_t o0 = b.op_off[c], o1 = b.op_off[c + 1];
-  const int nops = (int)(o1 - o0);
+  const int64_t o0 = b.op_off[c];
+  const int nops = (int)(b.op_off[c + 1] - o0);
   const bool whole = n <= C;
-  const int low = C - K;
-  auto emit = [&](int first, int count, std::vector<int>& hs) {
+  const int low = whole ? n : C - K;
+  const uint32_t lowmask = (1u << low) - 1u;
+  auto emit = [&](const std::vector<int>& gates, std::vector<int>& hs) {
     BSeg s;
     memset(&s, 0, sizeof(s));
-    s.first = first;
-    s.count = count;
+    s.first = (int32_t)recs.size();
+    s.count = (int32_t)gates.size();
     if (!whole) {
-      // fill up to K higher qubits with the lowest unused ones
       for (int q = low; q < n && (int)hs.size() < K; ++q)
         if (std::find(hs.begin(), hs.end(), q) == hs.end()) hs.push_back(q);
       std::sort(hs.begin(), hs.end());
@@ -418,58 +490,72 @@ void segment_circuit(const BatchImpl& b, int c, int C, int K, std::vector<BOp>& 
       if (whole || q < low) return q;
       return low + (int)(std::find(hs.begin(), hs.end(), q) - hs.begin());
     };
-    for (int g = first; g < first + count; ++g) {
+    for (int g : gates) {
       const HostOp& h = b.ops[o0 + g];
-      BOp& o = bops[bops.size() - nops + g];
-      o.lt = (uint8_t)local(h.target);
-      o.lc = h.control < 0 ? (uint8_t)0xFF : (uint8_t)local(h.control);
+      BRec r;
+      memset(&r, 0, sizeof(r));
+      r.kind = h.kind;
+      r.lt = (uint8_t)local(h.target);
+      r.lc = h.control < 0 ? (uint8_t)0xFF : (uint8_t)local(h.control);
+      r.rot = h.rot;
+      memcpy(r.m, &b.mats[(size_t)h.mat * 8], sizeof(r.m));
+      recs.push_back(r);
     }
     segs.push_back(s);
   };
-  for (int g = 0; g < nops; ++g) {
-    const HostOp& h = b.ops[o0 + g];
-    BOp o;
-    memset(&o, 0, sizeof(o));
-    o.kind = h.kind;
-    o.mat = h.mat;
-    o.rot = h.rot;
-    bops.push_back(o);
-  }
   if (whole) {
-    std::vector<int> none;
-    emit(0, nops, none);
+    std::vector<int> all(nops), none;
+    for (int g = 0; g < nops; ++g) all[g] = g;
+    if (nops) emit(all, none);
     return;
   }
-  std::vector<int> hs;
-  int first = 0;
-  for (int g = 0; g < nops; ++g) {
-    const HostOp& h = b.ops[o0 + g];
-    int need[2], nn = 0;
-    for (int q : {(int)h.target, (int)h.control})
-      if (q >= low && std::find(hs.begin(), hs.end(), q) == hs.end()) need[nn++] = q;
-    if (nn == 2 && need[0] == need[1]) nn = 1;
-    if ((int)hs.size() + nn > K) {
-      emit(first, g - first, hs);
-      hs.clear();
-      first = g;
-      nn = 0;
-      for (int q : {(int)h.target, (int)h.control})
-        if (q >= low) need[nn++] = q;
+  std::vector<char> placed(nops, 0);
+  std::vector<int> gates, blocked;
+  int first = 0;  // first unplaced gate
+  while (first < nops) {
+    gates.clear();
+    blocked.clear();
+    uint32_t hmask = 0;  // higher qubits taken by this segment
+    int scanned = 0;
+    for (int g = first; g < nops && scanned < kSegWindow; ++g) {
+      if (placed[g]) continue;
+      ++scanned;
+      const HostOp& h = b.ops[o0 + g];
+      bool free_to_move = true;
+      for (int x : blocked) {
+        const HostOp& o = b.ops[o0 + x];
+        if ((h.qmask & o.qmask) & ~(h.dmask & o.dmask)) {
+          free_to_move = false;
+          break;
+        }
+      }
+      const uint32_t need = h.qmask & ~lowmask;
+      if (free_to_move && __builtin_popcount(hmask | need) <= K) {
+        hmask |= need;
+        gates.push_back(g);
+        placed[g] = 1;
+        continue;
+      }
+      blocked.push_back(g);
+      if ((int)blocked.size() > kSegSkip) break;
     }
-    for (int j = 0; j < nn; ++j) hs.push_back(need[j]);
+    std::vector<int> hs;
+    for (int q = low; q < n; ++q)
+      if (hmask >> q & 1u) hs.push_back(q);
+    emit(gates, hs);
+    while (first < nops && placed[first]) ++first;
   }
-  if (nops > first) emit(first, nops - first, hs);
 }
 
 }  // namespace
 
-// Build and upload the schedule (circuits, gates, segments) for (C, K).
+// Build and upload the schedule (circuits, gate records, segments) for (C, K).
 static Status build_schedule(BatchImpl* b, int C, int K) {
   if (b->sched_C == C && b->sched_K == K) return Status::ok();
   std::vector<BCirc> circ(b->ncirc);
-  std::vector<BOp> bops;
+  std::vector<BRec> recs;
   std::vector<BSeg> segs;
-  bops.reserve(b->ops.size());
+  recs.reserve(b->ops.size());
   for (int c = 0; c < b->ncirc; ++c) {
     BCirc& cc = circ[c];
     memset(&cc, 0, sizeof(cc));
@@ -477,32 +563,35 @@ static Status build_schedule(BatchImpl* b, int C, int K) {
     cc.nops = (int32_t)(b->op_off[c + 1] - b->op_off[c]);
     cc.ngroups = b->ngroups[c];
     cc.nrot = b->nrot[c];
-    cc.op_off = b->op_off[c];
+    cc.rec_off = (int64_t)recs.size();
     cc.grp_off = b->grp_off[c];
     cc.rot_off = b->rot_off[c];
     cc.seg_off = (int64_t)segs.size();
-    segment_circuit(*b, c, C, K, bops, segs);
-    cc.nseg = (int32_t)(segs.size() - cc.seg_off);
-    // every gate position must lie inside the LDS-resident part
+    const size_t seg0 = segs.size();
+    segment_circuit(*b, c, C, K, recs, segs);
+    // segment starts relative to the circuit's first record
+    for (size_t s = seg0; s < segs.size(); ++s) segs[s].first -= (int32_t)cc.rec_off;
+    cc.nseg = (int32_t)(segs.size() - seg0);
+    // every gate exactly once, every position inside the LDS-resident part
+    if ((int64_t)recs.size() - cc.rec_off != cc.nops)
+      return fail_st(QS_EHIP, "batch schedule: gate count mismatch (internal error)");
     const int m = std::min(cc.n, C);
-    for (int64_t g = cc.op_off; g < cc.op_off + cc.nops; ++g)
-      if (bops[g].lt >= m || (bops[g].lc != 0xFF && bops[g].lc >= m))
+    for (int64_t g = cc.rec_off; g < (int64_t)recs.size(); ++g)
+      if (recs[g].lt >= m || (recs[g].lc != 0xFF && recs[g].lc >= m) || recs[g].lt == recs[g].lc)
         return fail_st(QS_EHIP, "batch schedule: gate outside its chunk (internal error)");
   }
   const size_t o_circ = 0;
-  const size_t o_ops = align256(o_circ + circ.size() * sizeof(BCirc));
-  const size_t o_segs = align256(o_ops + std::max<size_t>(1, bops.size()) * sizeof(BOp));
+  const size_t o_recs = align256(o_circ + circ.size() * sizeof(BCirc));
+  const size_t o_segs = align256(o_recs + std::max<size_t>(1, recs.size()) * sizeof(BRec));
   const size_t total = align256(o_segs + std::max<size_t>(1, segs.size()) * sizeof(BSeg));
   std::vector<char> blob(total, 0);
   memcpy(blob.data() + o_circ, circ.data(), circ.size() * sizeof(BCirc));
-  if (!bops.empty()) memcpy(blob.data() + o_ops, bops.data(), bops.size() * sizeof(BOp));
-  memcpy(blob.data() + o_segs, segs.data(), segs.size() * sizeof(BSeg));
+  if (!recs.empty()) memcpy(blob.data() + o_recs, recs.data(), recs.size() * sizeof(BRec));
+  if (!segs.empty()) memcpy(blob.data() + o_segs, segs.data(), segs.size() * sizeof(BSeg));
+  Status st = hip_status(hipStreamSynchronize(b->stream), "batch sync");  // earlier runs may read it
+  if (!st.good()) return st;
   if (b->sched_bytes < total) {
-    if (b->sched) {
-      Status st = hip_status(hipStreamSynchronize(b->stream), "batch sync");
-      if (!st.good()) return st;
-      (void)hipFree(b->sched);
-    }
+    if (b->sched) (void)hipFree(b->sched);
     b->sched = nullptr;
     b->sched_bytes = 0;
     b->sched_C = b->sched_K = -1;
@@ -511,22 +600,24 @@ static Status build_schedule(BatchImpl* b, int C, int K) {
       return fail_st(QS_ENOMEM, "batch schedule allocation failed");
     }
     b->sched_bytes = total;
-  } else {
-    // earlier runs may still read the old schedule
-    Status st = hip_status(hipStreamSynchronize(b->stream), "batch sync");
-    if (!st.good()) return st;
   }
-  Status st = hip_status(hipMemcpy(b->sched, blob.data(), total, hipMemcpyHostToDevice),
-                         "batch schedule upload");
+  st = hip_status(hipMemcpy(b->sched, blob.data(), total, hipMemcpyHostToDevice),
+                  "batch schedule upload");
   if (!st.good()) return st;
   char* a = (char*)b->sched;
   b->circ_dev = (const BCirc*)(a + o_circ);
-  b->ops_dev = (const BOp*)(a + o_ops);
+  b->recs_dev = (const BRec*)(a + o_recs);
   b->segs_dev = (const BSeg*)(a + o_segs);
   b->nseg_total = (int64_t)segs.size();
   b->sched_C = C;
   b->sched_K = K;
   return Status::ok();
+}
+
+// Whether a gate acts diagonally on its target for every parameter value.
+static bool diag_target(const XGate& g) {
+  if (g.param >= 0) return g.kind == QS_OP_RZ;
+  return g.m[2] == 0.0 && g.m[3] == 0.0 && g.m[4] == 0.0 && g.m[5] == 0.0;
 }
 
 Status batch_create(int dtype, int ncirc, const int32_t* n, const int64_t* op_off,
@@ -546,7 +637,6 @@ Status batch_create(int dtype, int ncirc, const int32_t* n, const int64_t* op_of
   b->ngroups.resize(ncirc);
   b->nrot.resize(ncirc);
   b->ops.reserve((size_t)op_off[ncirc]);
-  std::vector<double> mats;
   std::unordered_map<std::string, int32_t> fixed_index;  // identical fixed matrices shared
   std::vector<PauliGroup> groups;
   std::vector<PauliTerm> terms;
@@ -572,21 +662,27 @@ Status batch_create(int dtype, int ncirc, const int32_t* n, const int64_t* op_of
       h.control = (int8_t)g.control;
       h.param = g.param;
       h.rot = g.param >= 0 ? nr++ : -1;
+      h.qmask = 1u << g.target;
+      h.dmask = diag_target(g) ? 1u << g.target : 0u;
+      if (g.control >= 0) {
+        h.qmask |= 1u << g.control;
+        h.dmask |= 1u << g.control;
+      }
       if (g.param >= 0) {
-        h.mat = (int32_t)(mats.size() / 8);
-        mats.insert(mats.end(), g.m, g.m + 8);
+        h.mat = (int32_t)(b->mats.size() / 8);
+        b->mats.insert(b->mats.end(), g.m, g.m + 8);
       } else {
         const std::string key((const char*)g.m, sizeof(g.m));
         auto it = fixed_index.find(key);
         if (it == fixed_index.end()) {
-          it = fixed_index.emplace(key, (int32_t)(mats.size() / 8)).first;
-          mats.insert(mats.end(), g.m, g.m + 8);
+          it = fixed_index.emplace(key, (int32_t)(b->mats.size() / 8)).first;
+          b->mats.insert(b->mats.end(), g.m, g.m + 8);
         }
         h.mat = it->second;
       }
       b->ops.push_back(h);
     }
-    if (mats.size() / 8 > (size_t)INT32_MAX) return fail_st(QS_ERANGE, who + "too many gates");
+    if (b->mats.size() / 8 > (size_t)INT32_MAX) return fail_st(QS_ERANGE, who + "too many gates");
     b->nrot[c] = nr;
     rot_total += nr;
     PauliTable t;
@@ -616,21 +712,19 @@ Status batch_create(int dtype, int ncirc, const int32_t* n, const int64_t* op_of
     (void)hipGetLastError();
     return fail_st(QS_EHIP, "qs_batch_create: compute unit count unavailable");
   }
-  // static arena: mats | groups | terms | order (LPT, then input order)
-  const size_t o_mats = 0;
-  const size_t o_groups = align256(o_mats + std::max<size_t>(1, mats.size()) * sizeof(double));
+  // static arena: groups | terms | order (LPT, then input order)
+  const size_t o_groups = 0;
   const size_t o_terms = align256(o_groups + std::max<size_t>(1, groups.size()) * sizeof(PauliGroup));
   const size_t o_order = align256(o_terms + std::max<size_t>(1, terms.size()) * sizeof(PauliTerm));
   const size_t total = align256(o_order + 2 * (size_t)ncirc * sizeof(int32_t));
   std::vector<char> blob(total, 0);
-  if (!mats.empty()) memcpy(blob.data() + o_mats, mats.data(), mats.size() * sizeof(double));
   if (!groups.empty()) memcpy(blob.data() + o_groups, groups.data(), groups.size() * sizeof(PauliGroup));
   if (!terms.empty()) memcpy(blob.data() + o_terms, terms.data(), terms.size() * sizeof(PauliTerm));
   std::vector<int32_t> ord(2 * (size_t)ncirc);
   for (int c = 0; c < ncirc; ++c) ord[c] = ord[ncirc + c] = c;
   std::stable_sort(ord.begin(), ord.begin() + ncirc,
                    [&](int a, int c) { return b->cost[a] > b->cost[c]; });
-  memcpy(blob.data() + o_order, ord.data(), ord.size() * sizeof(int32_t));
+  if (ncirc) memcpy(blob.data() + o_order, ord.data(), ord.size() * sizeof(int32_t));
   if (hipMalloc(&b->stat, total) != hipSuccess) {
     (void)hipGetLastError();
     return fail_st(QS_ENOMEM, "qs_batch_create: arena allocation failed");
@@ -641,7 +735,6 @@ Status batch_create(int dtype, int ncirc, const int32_t* n, const int64_t* op_of
     return st;
   }
   char* a = (char*)b->stat;
-  b->mats_dev = (const double*)(a + o_mats);
   b->groups_dev = (const PauliGroup*)(a + o_groups);
   b->terms_dev = (const PauliTerm*)(a + o_terms);
   b->order_dev = (const int32_t*)(a + o_order);
@@ -702,7 +795,7 @@ Status batch_run(BatchImpl* b, const qs_batch_tuning* tune, double* energy, doub
   if (b->ncirc == 0) return Status::ok();
   Status st = build_schedule(b, C, K);
   if (!st.good()) return st;
-  const size_t lds = 2 * ((size_t)1 << C) * ab;
+  const size_t lds = 2 * ((size_t)1 << C) * ab + (size_t)kRecBlock * sizeof(BRec);
   const int NW = threads / 64;
   const uint64_t units = b->nmax > C ? 1ull << b->nmax : 0;
   const size_t slot = align256(2 * units * ab + (size_t)b->nrot_max * NW * sizeof(double));
@@ -727,9 +820,8 @@ Status batch_run(BatchImpl* b, const qs_batch_tuning* tune, double* energy, doub
   BatchDev d;
   memset(&d, 0, sizeof(d));
   d.circ = b->circ_dev;
-  d.ops = b->ops_dev;
+  d.recs = b->recs_dev;
   d.segs = b->segs_dev;
-  d.mats = b->mats_dev;
   d.groups = b->groups_dev;
   d.terms = b->terms_dev;
   d.order = b->order_dev + (order == 1 ? b->ncirc : 0);
