@@ -278,7 +278,9 @@ __device__ __forceinline__ void run_ops(R* re, R* im, R* lre, R* lim,
 
 __device__ __forceinline__ uint64_t tile_base(uint64_t tile, const FusedArgs& A) {
   uint64_t x = tile << A.L;
-  for (int h = 0; h < A.nh; ++h) x = insert0(x, A.hpos[h]);
+#pragma unroll
+  for (int h = 0; h < 8; ++h)
+    if (h < A.nh) x = insert0(x, A.hpos[h]);
   return x;
 }
 
