@@ -89,6 +89,30 @@ class EventTimer:
         return out
 
 
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the rocprofv3 PMC
+    summary committed under profiles/ (FETCH_SIZE and WRITE_SIZE, scaled by
+    the same counters on the STREAM-copy kernel), or None when there is no
+    such summary or the kernel's source has changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.startswith(("traffic_bytes_per_launch", "source_file", "source_sha256")):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    try:
+        src = os.path.join(ROOT, fields["source_file"])
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if sha != fields["source_sha256"]:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, OSError, ValueError):
+        return None
+
+
 def cpu_baseline(n_gpu: int, u, pairs, args):
     """The CPU oracle, as it stands, on a bounded sample of the same
     per-gate workload: H and U on four targets and two controlled-U gates."""
@@ -437,8 +461,11 @@ def main():
         v["mean_launch_ms"] = round(v["mean_launch_ms"], 4)
         v["step_s"] = round(v["step_s"], 4)
     dom = max(kernels, key=lambda k: kernels[k]["step_s"])
+    traffic = None
+    if dom.startswith("k_fused"):
+        traffic = measured_traffic(f"k_fused_{args.dtype}", f"n{n}")
     roof = {"kernel": dom, "bound": "hbm", "achieved": kernels[dom]["achieved_GBps"],
-            "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": kernels[dom]["frac"], "traffic": None,
+            "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": kernels[dom]["frac"], "traffic": traffic,
             "bytes_per_launch": kernels[dom]["bytes_per_launch"],
             "mean_launch_ms": kernels[dom]["mean_launch_ms"]}
 
