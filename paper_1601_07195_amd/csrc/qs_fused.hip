@@ -86,95 +86,90 @@ __device__ __forceinline__ uint64_t reg_global_off(const int8_t* q, int r) {
   return o;
 }
 
-// Gate on register bit K for every register pair (r, r | 2^K); a control on
-// register bit creg (uniform, -1 for none) skips the pairs whose control bit
-// is 0 (a uniform branch: r is a compile-time constant).
-template <int K, int RA, typename R>
-__device__ __forceinline__ void reg_gate(R* re, R* im, const Mat<R>& q, int creg) {
+// Gate on register bit K for every register pair (r, r | 2^K); with a
+// control on register bit CR (>= 0) only the pairs whose control bit is 1.
+// Both are compile-time constants: a pair that is skipped costs nothing and
+// no branch splits the tile's registers (a runtime per-pair branch makes the
+// compiler copy the whole tile at every merge).  Amplitudes stay (re, im)
+// adjacent in registers, as they are loaded, stored and moved through LDS.
+template <int K, int CR, int RA, typename T, typename R>
+__device__ __forceinline__ void reg_gate(T* a, const Mat<R>& q) {
 #pragma unroll
   for (int r = 0; r < RA; ++r) {
     if (r & (1 << K)) continue;
-    const int r1 = r | (1 << K);
-    if (creg >= 0 && !((r >> creg) & 1)) continue;
-    mat_apply(q, re[r], im[r], re[r1], im[r1]);
+    if (CR >= 0 && !((r >> CR) & 1)) continue;
+    pair_apply(q, a[r], a[r | (1 << K)]);
   }
 }
 
 // Im<lambda|P|psi> over the register pairs of bit K (P = X or Y).
-template <int K, int RA, typename R>
-__device__ __forceinline__ double reg_grad(const R* re, const R* im, const R* lr, const R* li,
-                                           int pauli) {
+template <int K, int RA, typename T>
+__device__ __forceinline__ double reg_grad(const T* a, const T* l, int pauli) {
   double g = 0.0;
 #pragma unroll
   for (int r = 0; r < RA; ++r) {
     if (r & (1 << K)) continue;
     const int r1 = r | (1 << K);
-    g += pair_grad(pauli, re[r], im[r], re[r1], im[r1], lr[r], li[r], lr[r1], li[r1]);
+    g += pair_grad(pauli, a[r].x, a[r].y, a[r1].x, a[r1].y, l[r].x, l[r].y, l[r1].x, l[r1].y);
   }
   return g;
 }
 
 // amplitude *= (dr + i di)
-template <typename R>
-__device__ __forceinline__ void cscale(R& xr, R& xi, R dr, R di) {
-  const R ar = dr * xr - di * xi;
-  xi = dr * xi + di * xr;
-  xr = ar;
+template <typename T, typename R>
+__device__ __forceinline__ void cscale(T& x, R dr, R di) {
+  const R xr = x.x, xi = x.y;
+  x = T{dr * xr - di * xi, dr * xi + di * xr};
 }
 
 template <typename R, int NREG>
-__device__ __forceinline__ void remap_tile(R* re, R* im, typename LdsAmp<R>::T* lds, int to,
-                                           const FMapDev* mo, int tn, const FMapDev* mn) {
+__device__ __forceinline__ void remap_tile(typename LdsAmp<R>::T* a, typename LdsAmp<R>::T* lds,
+                                           int to, const FMapDev* mo, int tn, const FMapDev* mn) {
   constexpr int RA = 1 << NREG;
-  using LT = typename LdsAmp<R>::T;
 #pragma unroll
-  for (int r = 0; r < RA; ++r) {
-    LT v;
-    v.x = re[r];
-    v.y = im[r];
-    lds[LdsAmp<R>::swz(to | mo->regoff[r])] = v;
-  }
+  for (int r = 0; r < RA; ++r) lds[LdsAmp<R>::swz(to | mo->regoff[r])] = a[r];
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < RA; ++r) {
-    const LT v = lds[LdsAmp<R>::swz(tn | mn->regoff[r])];
-    re[r] = v.x;
-    im[r] = v.y;
-  }
+  for (int r = 0; r < RA; ++r) a[r] = lds[LdsAmp<R>::swz(tn | mn->regoff[r])];
   __syncthreads();
 }
 
-template <typename R, int NREG>
-__device__ __forceinline__ void reg_gate_any(R* re, R* im, const Mat<R>& q, int creg, int k) {
+// Dispatch on (target register bit k, control register bit cr or -1): one
+// specialised, branch-free body per combination.
+template <typename R, int NREG, typename T>
+__device__ __forceinline__ void reg_gate_any(T* a, const Mat<R>& q, int cr, int k) {
   constexpr int RA = 1 << NREG;
-  switch (k) {
-    case 0: reg_gate<0, RA>(re, im, q, creg); break;
-    case 1: reg_gate<1, RA>(re, im, q, creg); break;
-    case 2: reg_gate<2, RA>(re, im, q, creg); break;
-    default:
-      if constexpr (NREG > 3) reg_gate<(NREG > 3 ? 3 : 0), RA>(re, im, q, creg);
-      break;
+  switch (k * 8 + cr + 1) {
+#define QS_REG_GATE(K, CR)                                                  \
+  case K * 8 + CR + 1:                                                      \
+    if constexpr (K < NREG && CR < NREG) reg_gate<K, CR, RA>(a, q);        \
+    break;
+    QS_REG_GATE(0, -1) QS_REG_GATE(0, 1) QS_REG_GATE(0, 2) QS_REG_GATE(0, 3)
+    QS_REG_GATE(1, -1) QS_REG_GATE(1, 0) QS_REG_GATE(1, 2) QS_REG_GATE(1, 3)
+    QS_REG_GATE(2, -1) QS_REG_GATE(2, 0) QS_REG_GATE(2, 1) QS_REG_GATE(2, 3)
+    QS_REG_GATE(3, -1) QS_REG_GATE(3, 0) QS_REG_GATE(3, 1) QS_REG_GATE(3, 2)
+#undef QS_REG_GATE
+    default: break;
   }
 }
 
-template <typename R, int NREG>
-__device__ __forceinline__ double reg_grad_any(const R* re, const R* im, const R* lr,
-                                               const R* li, int pauli, int k) {
+template <int NREG, typename T>
+__device__ __forceinline__ double reg_grad_any(const T* a, const T* l, int pauli, int k) {
   constexpr int RA = 1 << NREG;
   switch (k) {
-    case 0: return reg_grad<0, RA>(re, im, lr, li, pauli);
-    case 1: return reg_grad<1, RA>(re, im, lr, li, pauli);
-    case 2: return reg_grad<2, RA>(re, im, lr, li, pauli);
+    case 0: return reg_grad<0, RA>(a, l, pauli);
+    case 1: return reg_grad<1, RA>(a, l, pauli);
+    case 2: return reg_grad<2, RA>(a, l, pauli);
     default:
-      if constexpr (NREG > 3) return reg_grad<(NREG > 3 ? 3 : 0), RA>(re, im, lr, li, pauli);
+      if constexpr (NREG > 3) return reg_grad<(NREG > 3 ? 3 : 0), RA>(a, l, pauli);
       return 0.0;
   }
 }
 
 // Diagonal op on one register tile: amplitude *= d0 or d1 by its target bit.
-template <typename R, int NREG>
-__device__ __forceinline__ void diag_tile(R* re, R* im, R d0r, R d0i, R d1r, R d1i, int tw,
-                                          int tix, int creg, bool on, uint64_t base) {
+template <typename R, int NREG, typename T>
+__device__ __forceinline__ void diag_tile(T* a, R d0r, R d0i, R d1r, R d1i, int tw, int tix,
+                                          int creg, bool on, uint64_t base) {
   constexpr int RA = 1 << NREG;
   if (tw == kInReg) {
     // entries per register index: uniform, except for a thread control
@@ -187,7 +182,7 @@ __device__ __forceinline__ void diag_tile(R* re, R* im, R d0r, R d0i, R d1r, R d
       di = c_r ? di : (R)0;
       dr = on ? dr : (R)1;
       di = on ? di : (R)0;
-      cscale(re[r], im[r], dr, di);
+      cscale(a[r], dr, di);
     }
   } else {
     // target bit fixed for the whole thread (thread bit) or tile (outside)
@@ -197,7 +192,7 @@ __device__ __forceinline__ void diag_tile(R* re, R* im, R d0r, R d0i, R d1r, R d
 #pragma unroll
     for (int r = 0; r < RA; ++r) {
       const bool c_r = creg < 0 || ((r >> creg) & 1);  // uniform
-      cscale(re[r], im[r], c_r ? tr : (R)1, c_r ? ti : (R)0);
+      cscale(a[r], c_r ? tr : (R)1, c_r ? ti : (R)0);
     }
   }
 }
@@ -214,7 +209,7 @@ __device__ __forceinline__ void diag_tile(R* re, R* im, R d0r, R d0i, R d1r, R d
 // X/Y on register pairs, Z by the sign of the target bit) to the wave's LDS
 // accumulator of that slot.
 template <typename R, int NREG, bool ADJ>
-__device__ __forceinline__ void run_ops(R* re, R* im, R* lre, R* lim,
+__device__ __forceinline__ void run_ops(typename LdsAmp<R>::T* a, typename LdsAmp<R>::T* l,
                                         typename LdsAmp<R>::T* lds, const FOp* __restrict__ ops,
                                         int nops, const FMapDev* __restrict__ maps,
                                         uint64_t base, double* acc) {
@@ -227,32 +222,47 @@ __device__ __forceinline__ void run_ops(R* re, R* im, R* lre, R* lim,
       const FMapDev* mo = maps + uniform(aux);
       const FMapDev* mn = maps + uniform(tgt);
       const int to = thr_tile_off(mo->thr_pack), tn = thr_tile_off(mn->thr_pack);
-      remap_tile<R, NREG>(re, im, lds, to, mo, tn, mn);
-      if constexpr (ADJ) remap_tile<R, NREG>(lre, lim, lds, to, mo, tn, mn);
+      remap_tile<R, NREG>(a, lds, to, mo, tn, mn);
+      if constexpr (ADJ) remap_tile<R, NREG>(l, lds, to, mo, tn, mn);
       continue;
     }
     const int cw = ctl >> 8, ci = ctl & 255;
-    if (cw == kOutside && !((base >> ci) & 1)) continue;  // per-tile predicate (uniform)
     const int creg = (cw == kInReg) ? ci : -1;
     const bool on = (cw == kInThread) ? (bool)((threadIdx.x >> ci) & 1) : true;
     if (kind == kOpU) {
+      // a control outside the tile selects the identity for the whole tile
+      // (uniform), a thread-index control per lane: no branch around the
+      // gate, so the tile stays in its registers
+      const bool tile_on = cw != kOutside || ((base >> ci) & 1);
       Mat<R> q;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        q.r[e] = (R)op->m[2 * e];
-        q.i[e] = (R)op->m[2 * e + 1];
+        const R one = (e == 0 || e == 3) ? (R)1 : (R)0;
+        q.r[e] = tile_on ? (R)op->m[2 * e] : one;
+        q.i[e] = tile_on ? (R)op->m[2 * e + 1] : (R)0;
       }
       if constexpr (ADJ) {
         if (aux >= 0) {  // rotation (never controlled): gradient before the inverse
-          const double g = wave_sum(reg_grad_any<R, NREG>(re, im, lre, lim, pauli, tgt));
+          const double g = wave_sum(reg_grad_any<NREG>(a, l, pauli, tgt));
           if ((threadIdx.x & 63) == 0) acc[aux * 4 + (threadIdx.x >> 6)] += g;
         }
       }
-      if (on) {  // a thread-index control: the only lane-dependent branch
-        reg_gate_any<R, NREG>(re, im, q, creg, tgt);
-        if constexpr (ADJ) reg_gate_any<R, NREG>(lre, lim, q, creg, tgt);
+      if (cw == kInThread) {
+        Mat<R> ql;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const R one = (e == 0 || e == 3) ? (R)1 : (R)0;
+          ql.r[e] = on ? q.r[e] : one;
+          ql.i[e] = on ? q.i[e] : (R)0;
+        }
+        reg_gate_any<R, NREG>(a, ql, -1, tgt);
+        if constexpr (ADJ) reg_gate_any<R, NREG>(l, ql, -1, tgt);
+      } else {
+        reg_gate_any<R, NREG>(a, q, creg, tgt);
+        if constexpr (ADJ) reg_gate_any<R, NREG>(l, q, creg, tgt);
       }
     } else {  // diagonal
+      if (cw == kOutside && !((base >> ci) & 1)) continue;  // per-tile predicate (uniform)
       const R d0r = (R)op->m[0], d0i = (R)op->m[1], d1r = (R)op->m[6], d1i = (R)op->m[7];
       const int tw = tgt >> 8, tix = tgt & 255;
       if constexpr (ADJ) {
@@ -263,15 +273,15 @@ __device__ __forceinline__ void run_ops(R* re, R* im, R* lre, R* lim,
 #pragma unroll
           for (int r = 0; r < RA; ++r) {
             const bool bit = (tw == kInReg) ? (bool)((r >> tix) & 1) : fixed_bit;
-            const double t = im_conj_mul(lre[r], lim[r], re[r], im[r]);
+            const double t = im_conj_mul(l[r].x, l[r].y, a[r].x, a[r].y);
             g += bit ? -t : t;
           }
           g = wave_sum(g);
           if ((threadIdx.x & 63) == 0) acc[aux * 4 + (threadIdx.x >> 6)] += g;
         }
       }
-      diag_tile<R, NREG>(re, im, d0r, d0i, d1r, d1i, tw, tix, creg, on, base);
-      if constexpr (ADJ) diag_tile<R, NREG>(lre, lim, d0r, d0i, d1r, d1i, tw, tix, creg, on, base);
+      diag_tile<R, NREG>(a, d0r, d0i, d1r, d1i, tw, tix, creg, on, base);
+      if constexpr (ADJ) diag_tile<R, NREG>(l, d0r, d0i, d1r, d1i, tw, tix, creg, on, base);
     }
   }
 }
@@ -294,20 +304,15 @@ k_fused_c128(d2* __restrict__ a, FusedArgs A, const FOp* __restrict__ ops,
              const FMapDev* __restrict__ maps) {
   constexpr int RA = 1 << NREG;
   __shared__ d2 lds[RA * kFuseBlock];
-  double re[RA], im[RA];
+  d2 t[RA];
   const uint64_t tl = thr_global_off(A.ld_thr), ts = thr_global_off(A.st_thr);
   for (uint64_t tile = blockIdx.x; tile < A.ntiles; tile += gridDim.x) {
     const uint64_t base = tile_base(tile, A);
 #pragma unroll
-    for (int r = 0; r < RA; ++r) {
-      const d2 v = gload<true>(a + (base | tl | reg_global_off<NREG>(A.ld_reg, r)));
-      re[r] = v.x;
-      im[r] = v.y;
-    }
-    run_ops<double, NREG, false>(re, im, nullptr, nullptr, lds, ops, A.nops, maps, base, nullptr);
+    for (int r = 0; r < RA; ++r) t[r] = gload<true>(a + (base | tl | reg_global_off<NREG>(A.ld_reg, r)));
+    run_ops<double, NREG, false>(t, nullptr, lds, ops, A.nops, maps, base, nullptr);
 #pragma unroll
-    for (int r = 0; r < RA; ++r)
-      gstore<true>(a + (base | ts | reg_global_off<NREG>(A.st_reg, r)), d2{re[r], im[r]});
+    for (int r = 0; r < RA; ++r) gstore<true>(a + (base | ts | reg_global_off<NREG>(A.st_reg, r)), t[r]);
   }
 }
 
@@ -319,23 +324,21 @@ k_fused_c64(f4* __restrict__ a, FusedArgs A, const FOp* __restrict__ ops,
             const FMapDev* __restrict__ maps) {
   constexpr int RA = 1 << NREG;
   __shared__ f2 lds[RA * kFuseBlock];
-  float re[RA], im[RA];
+  f2 t[RA];
   const uint64_t tl = thr_global_off(A.ld_thr), ts = thr_global_off(A.st_thr);
   for (uint64_t tile = blockIdx.x; tile < A.ntiles; tile += gridDim.x) {
     const uint64_t base = tile_base(tile, A);
 #pragma unroll
     for (int r = 0; r < RA; r += 2) {
       const f4 v = gload<true>(a + ((base | tl | reg_global_off<NREG>(A.ld_reg, r)) >> 1));
-      re[r] = v.x;
-      im[r] = v.y;
-      re[r + 1] = v.z;
-      im[r + 1] = v.w;
+      t[r] = f2{v.x, v.y};
+      t[r + 1] = f2{v.z, v.w};
     }
-    run_ops<float, NREG, false>(re, im, nullptr, nullptr, lds, ops, A.nops, maps, base, nullptr);
+    run_ops<float, NREG, false>(t, nullptr, lds, ops, A.nops, maps, base, nullptr);
 #pragma unroll
     for (int r = 0; r < RA; r += 2)
       gstore<true>(a + ((base | ts | reg_global_off<NREG>(A.st_reg, r)) >> 1),
-                   f4{re[r], im[r], re[r + 1], im[r + 1]});
+                   f4{t[r].x, t[r].y, t[r + 1].x, t[r + 1].y});
   }
 }
 
@@ -353,25 +356,22 @@ k_fused_adj_c128(d2* __restrict__ psi, d2* __restrict__ lam, FusedArgs A,
   __shared__ double acc[kAdjMaxSlots * 4];
   for (int i = threadIdx.x; i < kAdjMaxSlots * 4; i += kFuseBlock) acc[i] = 0.0;
   __syncthreads();
-  double re[RA], im[RA], lre[RA], lim[RA];
+  d2 t[RA], l[RA];
   const uint64_t tl = thr_global_off(A.ld_thr), ts = thr_global_off(A.st_thr);
   for (uint64_t tile = blockIdx.x; tile < A.ntiles; tile += gridDim.x) {
     const uint64_t base = tile_base(tile, A);
 #pragma unroll
     for (int r = 0; r < RA; ++r) {
       const uint64_t i = base | tl | reg_global_off<NREG>(A.ld_reg, r);
-      const d2 v = gload<true>(psi + i), w = gload<true>(lam + i);
-      re[r] = v.x;
-      im[r] = v.y;
-      lre[r] = w.x;
-      lim[r] = w.y;
+      t[r] = gload<true>(psi + i);
+      l[r] = gload<true>(lam + i);
     }
-    run_ops<double, NREG, true>(re, im, lre, lim, lds, ops, A.nops, maps, base, acc);
+    run_ops<double, NREG, true>(t, l, lds, ops, A.nops, maps, base, acc);
 #pragma unroll
     for (int r = 0; r < RA; ++r) {
       const uint64_t i = base | ts | reg_global_off<NREG>(A.st_reg, r);
-      gstore<true>(psi + i, d2{re[r], im[r]});
-      gstore<true>(lam + i, d2{lre[r], lim[r]});
+      gstore<true>(psi + i, t[r]);
+      gstore<true>(lam + i, l[r]);
     }
   }
   __syncthreads();
@@ -381,7 +381,7 @@ k_fused_adj_c128(d2* __restrict__ psi, d2* __restrict__ lam, FusedArgs A,
 }
 
 template <int NREG>
-__global__ void __launch_bounds__(kFuseBlock)
+__global__ void __launch_bounds__(kFuseBlock, 2)  // two waves per SIMD: at most 256 registers
 k_fused_adj_c64(f4* __restrict__ psi, f4* __restrict__ lam, FusedArgs A,
                 const FOp* __restrict__ ops, const FMapDev* __restrict__ maps,
                 double* __restrict__ part) {
@@ -390,7 +390,7 @@ k_fused_adj_c64(f4* __restrict__ psi, f4* __restrict__ lam, FusedArgs A,
   __shared__ double acc[kAdjMaxSlots * 4];
   for (int i = threadIdx.x; i < kAdjMaxSlots * 4; i += kFuseBlock) acc[i] = 0.0;
   __syncthreads();
-  float re[RA], im[RA], lre[RA], lim[RA];
+  f2 t[RA], l[RA];
   const uint64_t tl = thr_global_off(A.ld_thr), ts = thr_global_off(A.st_thr);
   for (uint64_t tile = blockIdx.x; tile < A.ntiles; tile += gridDim.x) {
     const uint64_t base = tile_base(tile, A);
@@ -398,15 +398,17 @@ k_fused_adj_c64(f4* __restrict__ psi, f4* __restrict__ lam, FusedArgs A,
     for (int r = 0; r < RA; r += 2) {
       const uint64_t u = (base | tl | reg_global_off<NREG>(A.ld_reg, r)) >> 1;
       const f4 v = gload<true>(psi + u), w = gload<true>(lam + u);
-      re[r] = v.x; im[r] = v.y; re[r + 1] = v.z; im[r + 1] = v.w;
-      lre[r] = w.x; lim[r] = w.y; lre[r + 1] = w.z; lim[r + 1] = w.w;
+      t[r] = f2{v.x, v.y};
+      t[r + 1] = f2{v.z, v.w};
+      l[r] = f2{w.x, w.y};
+      l[r + 1] = f2{w.z, w.w};
     }
-    run_ops<float, NREG, true>(re, im, lre, lim, lds, ops, A.nops, maps, base, acc);
+    run_ops<float, NREG, true>(t, l, lds, ops, A.nops, maps, base, acc);
 #pragma unroll
     for (int r = 0; r < RA; r += 2) {
       const uint64_t u = (base | ts | reg_global_off<NREG>(A.st_reg, r)) >> 1;
-      gstore<true>(psi + u, f4{re[r], im[r], re[r + 1], im[r + 1]});
-      gstore<true>(lam + u, f4{lre[r], lim[r], lre[r + 1], lim[r + 1]});
+      gstore<true>(psi + u, f4{t[r].x, t[r].y, t[r + 1].x, t[r + 1].y});
+      gstore<true>(lam + u, f4{l[r].x, l[r].y, l[r + 1].x, l[r + 1].y});
     }
   }
   __syncthreads();
