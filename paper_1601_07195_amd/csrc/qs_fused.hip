@@ -214,8 +214,13 @@ __device__ __forceinline__ void run_ops(typename LdsAmp<R>::T* a, typename LdsAm
                                         int nops, const FMapDev* __restrict__ maps,
                                         uint64_t base, double* acc) {
   constexpr int RA = 1 << NREG;
+  // The next op's record is fetched (scalar loads) while this op computes;
+  // the table holds one spare record past every pass's last op.
+  FOp nxt = ops[0];
   for (int oi = 0; oi < nops; ++oi) {
-    const FOp* op = ops + uniform(oi);
+    const FOp cur = nxt;
+    nxt = ops[uniform(oi + 1)];
+    const FOp* op = &cur;
     const int kw = op->kind, tgt = op->tgt, ctl = op->ctl, aux = op->aux;
     const int kind = kw & 255, pauli = kw >> 8;
     if (kind == kOpRemap) {
@@ -450,9 +455,10 @@ static Status upload_plan(StateImpl* s, const Plan& plan, const FuseGeom& G, con
   if (plan.ops.empty()) return Status::ok();
   std::vector<FMapDev> md;
   for (const FMap& m : plan.maps) md.push_back(fmap_dev(m, G.nreg));
-  const size_t ob = plan.ops.size() * sizeof(FOp), mb = md.size() * sizeof(FMapDev);
-  std::vector<char> blob(ob + mb);
-  memcpy(blob.data(), plan.ops.data(), ob);
+  // one zeroed record past the last op: the kernels prefetch op i + 1
+  const size_t ob = (plan.ops.size() + 1) * sizeof(FOp), mb = md.size() * sizeof(FMapDev);
+  std::vector<char> blob(ob + mb, 0);
+  memcpy(blob.data(), plan.ops.data(), plan.ops.size() * sizeof(FOp));
   memcpy(blob.data() + ob, md.data(), mb);
   Status st = upload_table(s, blob.data(), blob.size());
   if (!st.good()) return st;
