@@ -32,30 +32,36 @@ struct FusedArgs {
 };
 
 // Device form of an FMap for LDS remaps: tile bit of thread-index bit i in
-// nibble i of thr_pack; tile-local offset of register index r in regoff[r].
+// nibble i of thr_pack; regoff[r]: byte offset in the remap buffer of the
+// register-index part of register r's tile position, already swizzled (the
+// swizzle is linear over XOR, and thread and register parts of a position
+// have disjoint bits, so a lane's address is swz(thread part) ^ regoff[r]).
 struct FMapDev {
   uint32_t thr_pack;
   uint32_t pad[3];
   int32_t regoff[32];
 };
 
+// LDS remap buffer swizzle (bank-conflict-free remaps): the element index
+// with its higher chunks XOR-folded into the low chunk; shared by the host
+// (register offsets) and the device (thread offsets).
+__host__ __device__ __forceinline__ int swz_c128(int j) {  // 16-byte elements, 3-bit chunks
+  return j ^ (((j >> 3) ^ (j >> 6) ^ (j >> 9)) & 7);
+}
+__host__ __device__ __forceinline__ int swz_c64(int j) {  // 8-byte elements, 4-bit chunks
+  return j ^ (((j >> 4) ^ (j >> 8) ^ (j >> 12)) & 15);
+}
 template <typename R>
 struct LdsAmp;
 template <>
 struct LdsAmp<double> {
   using T = d2;
-  // 16-byte elements: fold 3-bit chunks of the index into its low 3 bits
-  static __device__ __forceinline__ int swz(int j) {
-    return j ^ (((j >> 3) ^ (j >> 6) ^ (j >> 9)) & 7);
-  }
+  static __device__ __forceinline__ int swz(int j) { return swz_c128(j); }
 };
 template <>
 struct LdsAmp<float> {
   using T = f2;
-  // 8-byte elements: fold 4-bit chunks into the low 4 bits
-  static __device__ __forceinline__ int swz(int j) {
-    return j ^ (((j >> 4) ^ (j >> 8) ^ (j >> 12)) & 15);
-  }
+  static __device__ __forceinline__ int swz(int j) { return swz_c64(j); }
 };
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -122,15 +128,18 @@ __device__ __forceinline__ void cscale(T& x, R dr, R di) {
   x = T{dr * xr - di * xi, dr * xi + di * xr};
 }
 
+// to, tn: this lane's swizzled byte offsets under the old and new mapping.
 template <typename R, int NREG>
 __device__ __forceinline__ void remap_tile(typename LdsAmp<R>::T* a, typename LdsAmp<R>::T* lds,
                                            int to, const FMapDev* mo, int tn, const FMapDev* mn) {
+  using LT = typename LdsAmp<R>::T;
   constexpr int RA = 1 << NREG;
+  char* base = (char*)lds;
 #pragma unroll
-  for (int r = 0; r < RA; ++r) lds[LdsAmp<R>::swz(to | mo->regoff[r])] = a[r];
+  for (int r = 0; r < RA; ++r) *(LT*)(base + (to ^ mo->regoff[r])) = a[r];
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < RA; ++r) a[r] = lds[LdsAmp<R>::swz(tn | mn->regoff[r])];
+  for (int r = 0; r < RA; ++r) a[r] = *(const LT*)(base + (tn ^ mn->regoff[r]));
   __syncthreads();
 }
 
@@ -226,7 +235,9 @@ __device__ __forceinline__ void run_ops(typename LdsAmp<R>::T* a, typename LdsAm
     if (kind == kOpRemap) {
       const FMapDev* mo = maps + uniform(aux);
       const FMapDev* mn = maps + uniform(tgt);
-      const int to = thr_tile_off(mo->thr_pack), tn = thr_tile_off(mn->thr_pack);
+      constexpr int ES = (int)sizeof(typename LdsAmp<R>::T);
+      const int to = LdsAmp<R>::swz(thr_tile_off(mo->thr_pack)) * ES;
+      const int tn = LdsAmp<R>::swz(thr_tile_off(mn->thr_pack)) * ES;
       remap_tile<R, NREG>(a, lds, to, mo, tn, mn);
       if constexpr (ADJ) remap_tile<R, NREG>(l, lds, to, mo, tn, mn);
       continue;
@@ -253,15 +264,23 @@ __device__ __forceinline__ void run_ops(typename LdsAmp<R>::T* a, typename LdsAm
         }
       }
       if (cw == kInThread) {
-        Mat<R> ql;
+        if constexpr (ADJ) {
+          // two tiles: masking the lanes off costs less than per-lane
+          // coefficients for both (measured)
+          if (on) {
+            reg_gate_any<R, NREG>(a, q, -1, tgt);
+            reg_gate_any<R, NREG>(l, q, -1, tgt);
+          }
+        } else {
+          Mat<R> ql;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const R one = (e == 0 || e == 3) ? (R)1 : (R)0;
-          ql.r[e] = on ? q.r[e] : one;
-          ql.i[e] = on ? q.i[e] : (R)0;
+          for (int e = 0; e < 4; ++e) {
+            const R one = (e == 0 || e == 3) ? (R)1 : (R)0;
+            ql.r[e] = on ? q.r[e] : one;
+            ql.i[e] = on ? q.i[e] : (R)0;
+          }
+          reg_gate_any<R, NREG>(a, ql, -1, tgt);
         }
-        reg_gate_any<R, NREG>(a, ql, -1, tgt);
-        if constexpr (ADJ) reg_gate_any<R, NREG>(l, ql, -1, tgt);
       } else {
         reg_gate_any<R, NREG>(a, q, creg, tgt);
         if constexpr (ADJ) reg_gate_any<R, NREG>(l, q, creg, tgt);
@@ -423,15 +442,16 @@ k_fused_adj_c64(f4* __restrict__ psi, f4* __restrict__ lam, FusedArgs A,
 }
 
 // Host: device tables of a plan's mappings.
-static FMapDev fmap_dev(const FMap& m, int nreg) {
+static FMapDev fmap_dev(const FMap& m, int nreg, int dtype) {
   FMapDev d;
   memset(&d, 0, sizeof(d));
   for (int i = 0; i < kFuseThreadBits; ++i) d.thr_pack |= (uint32_t)(m.thr[i] & 15) << (4 * i);
+  const int es = dtype == QS_C128 ? 16 : 8;
   for (int r = 0; r < (1 << nreg); ++r) {
     int o = 0;
     for (int k = 0; k < nreg; ++k)
       if ((r >> k) & 1) o |= 1 << m.reg[k];
-    d.regoff[r] = o;
+    d.regoff[r] = (dtype == QS_C128 ? swz_c128(o) : swz_c64(o)) * es;
   }
   return d;
 }
@@ -454,7 +474,7 @@ static Status upload_plan(StateImpl* s, const Plan& plan, const FuseGeom& G, con
   *dmaps = nullptr;
   if (plan.ops.empty()) return Status::ok();
   std::vector<FMapDev> md;
-  for (const FMap& m : plan.maps) md.push_back(fmap_dev(m, G.nreg));
+  for (const FMap& m : plan.maps) md.push_back(fmap_dev(m, G.nreg, s->dtype));
   // one zeroed record past the last op: the kernels prefetch op i + 1
   const size_t ob = (plan.ops.size() + 1) * sizeof(FOp), mb = md.size() * sizeof(FMapDev);
   std::vector<char> blob(ob + mb, 0);
