@@ -246,16 +246,16 @@ __device__ __forceinline__ void run_ops(typename LdsAmp<R>::T* a, typename LdsAm
     const int creg = (cw == kInReg) ? ci : -1;
     const bool on = (cw == kInThread) ? (bool)((threadIdx.x >> ci) & 1) : true;
     if (kind == kOpU) {
-      // a control outside the tile selects the identity for the whole tile
-      // (uniform), a thread-index control per lane: no branch around the
-      // gate, so the tile stays in its registers
-      const bool tile_on = cw != kOutside || ((base >> ci) & 1);
+      // a control outside the tile skips the gate for the whole tile (a
+      // uniform branch; the specialised bodies update the tile in place, so
+      // the skip costs no register copies); a thread-index control selects
+      // identity coefficients per lane
+      if (cw == kOutside && !((base >> ci) & 1)) continue;  // per-tile predicate (uniform)
       Mat<R> q;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const R one = (e == 0 || e == 3) ? (R)1 : (R)0;
-        q.r[e] = tile_on ? (R)op->m[2 * e] : one;
-        q.i[e] = tile_on ? (R)op->m[2 * e + 1] : (R)0;
+        q.r[e] = (R)op->m[2 * e];
+        q.i[e] = (R)op->m[2 * e + 1];
       }
       if constexpr (ADJ) {
         if (aux >= 0) {  // rotation (never controlled): gradient before the inverse
