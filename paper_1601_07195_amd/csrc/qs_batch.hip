@@ -22,13 +22,20 @@
 // neither the state nor, since commuting rotations keep their own
 // generator, the gradient.
 //
-// Gate records (kind, positions, matrix) of each block of up to kRecBlock
-// gates are staged in LDS before use, so a gate costs LDS reads only.
+// Inside a segment (or a whole LDS-resident state) the gates are grouped
+// into register blocks: consecutive gates (again allowing moves past
+// commuting gates) whose qubits fit in one set of three.  Each thread loads
+// the 8 amplitudes of its 3-qubit sub-cube from LDS into registers, applies
+// every gate of the block there, and stores them back: one LDS round trip
+// and one barrier per block instead of per gate.  A gate's body is
+// specialised at compile time for its (target, control) register bits.
 //
 // Gradient contributions are double precision: each wavefront reduces its
 // lanes by butterfly and adds the result to its own slot of the rotation's
-// row in the workspace; at the end of the circuit the workgroup adds the
-// wave slots in a fixed order.  Results are bitwise reproducible.
+// row in the workspace with a no-return atomic (only that wave's first lane
+// touches the slot, so the adds apply in program order); at the end of the
+// circuit the workgroup adds the wave slots in a fixed order.  Results are
+// bitwise reproducible.
 #include <string.h>
 
 #include <algorithm>
@@ -46,33 +53,50 @@ namespace qs {
 // Device description of one circuit.
 struct BCirc {
   int32_t n, nops, nseg, ngroups;
-  int32_t nrot, pad;
-  int64_t rec_off, seg_off, grp_off, rot_off;
+  int32_t nrot, nblk;
+  int64_t rec_off, seg_off, grp_off, rot_off, blk_off;
 };
-// One gate in execution order: generator kind, target and control as bit
-// positions inside the gate's segment (the qubit itself when the whole
-// state is in LDS), the rotation's ordinal in its circuit (-1: not a
-// rotation) and the matrix applied in the forward sweep.
+// Matrix forms with cheaper register updates than a general complex 2x2
+// (the conjugate transpose of each form has the same form).
+enum BForm : uint8_t {
+  kFormGen = 0,   // general complex
+  kFormReal = 1,  // real entries (RY, H, X)
+  kFormDiag = 2,  // diagonal (RZ, phases)
+  kFormSwap = 3,  // exactly X under a control (CNOT): a register exchange
+};
+// One gate in execution order: generator kind, target and control as bits
+// of its register block (0..2; control 0xFF: none), matrix form, the
+// rotation's ordinal in its circuit (-1: not a rotation) and the matrix
+// applied in the forward sweep.
 struct BRec {
-  uint8_t kind, lt, lc, pad;  // lc = 0xFF: no control
+  uint8_t kind, rt, rc, form;
   int32_t rot;
   int32_t pad2[2];
   double m[8];
 };
 static_assert(sizeof(BRec) == 80, "gate record layout");
-// Segment: records [first, first + count) of its circuit; hpos: the K
-// higher qubits (ascending) held by chunk bits C - K .. C - 1.
+// Register block: gate records [first, first + count) of its circuit, and
+// the three LDS-resident bit positions q[0] < q[1] < q[2] held by register
+// bits 0, 1, 2.
+struct BBlk {
+  int32_t first, count;
+  uint8_t q[4];
+  int32_t pad;
+};
+static_assert(sizeof(BBlk) == 16, "block record layout");
+// Segment: blocks [first, first + count) of its circuit; hpos: the K higher
+// qubits (ascending) held by chunk bits C - K .. C - 1.
 struct BSeg {
   int32_t first, count;
   uint8_t hpos[8];
 };
 
 constexpr int kBatchMaxHigh = 8;
-constexpr int kRecBlock = 64;  // gate records staged in LDS at a time
 
 struct BatchDev {
   const BCirc* circ;
   const BRec* recs;
+  const BBlk* blks;
   const BSeg* segs;
   const PauliGroup* groups;
   const PauliTerm* terms;   // PauliGroup::first is global into this array
@@ -91,18 +115,50 @@ struct BatchDev {
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Copy of *p read through the constant address space: with a uniform p the
+// compiler uses scalar loads and keeps the fields in scalar registers (a
+// plain load may not, since the kernel writes global memory).  Only for the
+// schedule tables, which nothing writes while the kernel runs.
+template <typename X>
+__device__ __forceinline__ X ldc(const X* p) {
+  static_assert(sizeof(X) % 4 == 0, "word-sized table entries");
+  typedef const __attribute__((address_space(4))) uint32_t cword;
+  uint32_t w[sizeof(X) / 4];
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(X) / 4); ++i) w[i] = ((cword*)p)[i];
+  X v;
+  __builtin_memcpy(&v, w, sizeof(X));
+  return v;
+}
+
 __device__ __forceinline__ uint32_t ins0(uint32_t p, int k) {
   const uint32_t lo = p & ((1u << k) - 1u);
   return ((p ^ lo) << 1) | lo;
 }
-// First index of the pair of work item p for a gate on target t (control c
-// or -1): a 0 inserted at t (and at c, whose bit is then set).
-__device__ __forceinline__ uint32_t pair_base32(uint32_t p, int t, int c) {
-  if (c < 0) return ins0(p, t);
-  const int lo = c < t ? c : t, hi = c < t ? t : c;
-  return ins0(ins0(p, lo), hi) | (1u << c);
-}
 
+// LDS slot of amplitude index j: the higher chunks of j XOR-folded into its
+// low chunk (3 bits for 16-byte, 4 bits for 8-byte amplitudes), so that the
+// lanes of a wave reach distinct banks whatever bits a register block
+// strides over.  The map is XOR-linear, so the slot of (a | b) for disjoint
+// a and b is slot(a) ^ slot(b), and a bijection on every [0, 2^m).
+template <typename T>
+struct Swz;
+template <>
+struct Swz<d2> {
+  static __device__ __forceinline__ uint32_t f(uint32_t j) {
+    return j ^ (((j >> 3) ^ (j >> 6) ^ (j >> 9) ^ (j >> 12)) & 7u);
+  }
+};
+template <>
+struct Swz<f2> {
+  static __device__ __forceinline__ uint32_t f(uint32_t j) {
+    return j ^ (((j >> 4) ^ (j >> 8) ^ (j >> 12)) & 15u);
+  }
+};
+// Identity map, for states in global memory.
+struct NoSwz {
+  static __device__ __forceinline__ uint32_t f(uint32_t j) { return j; }
+};
 // The record's matrix, or its conjugate transpose, in compute precision.
 template <typename R>
 __device__ __forceinline__ void rec_mat(const BRec& r, bool dag, Mat<R>& q) {
@@ -120,72 +176,194 @@ __device__ __forceinline__ void rec_mat(const BRec& r, bool dag, Mat<R>& q) {
   }
 }
 
-// q on (t, c) for a 2^m-amplitude array in LDS; V pairs per thread in flight.
-template <typename R, typename T, int B>
-__device__ __forceinline__ void lds_gate(T* a, int m, int t, int c, const Mat<R>& q) {
-  constexpr int V = 2;
-  const uint32_t items = 1u << (m - (c >= 0 ? 2 : 1));
-  const uint32_t s = 1u << t;
-  for (uint32_t p0 = threadIdx.x; p0 < items; p0 += B * V) {
-    T x[V], y[V];
-    uint32_t i0[V];
+// Gate on register bit K of an 8-amplitude register block.  With a control
+// on register bit rc (>= 0) the pairs whose control bit is 0 take the
+// identity; rc is uniform, so the coefficients are chosen with scalar
+// selects and every pair runs the same arithmetic.
+template <int K, typename T, typename R>
+__device__ __forceinline__ void blk_gate(T* x, const Mat<R>& q, int rc) {
 #pragma unroll
-    for (int v = 0; v < V; ++v) {
-      i0[v] = pair_base32(p0 + v * B, t, c);
-      if (p0 + v * B < items) {
-        x[v] = a[i0[v]];
-        y[v] = a[i0[v] + s];
-      }
-    }
+  for (int r = 0; r < 8; ++r) {
+    if (r & (1 << K)) continue;
+    const bool on = rc < 0 || ((r >> rc) & 1);
+    Mat<R> u;
 #pragma unroll
-    for (int v = 0; v < V; ++v) {
-      if (p0 + v * B < items) {
-        pair_apply(q, x[v], y[v]);
-        a[i0[v]] = x[v];
-        a[i0[v] + s] = y[v];
-      }
+    for (int e = 0; e < 4; ++e) {
+      const R id = (e == 0 || e == 3) ? (R)1 : (R)0;
+      u.r[e] = on ? q.r[e] : id;
+      u.i[e] = on ? q.i[e] : (R)0;
     }
+    pair_apply(u, x[r], x[r | (1 << K)]);
+  }
+}
+// Uncontrolled forms on register bit K.
+template <int K, typename T, typename R>
+__device__ __forceinline__ void blk_gen(T* x, const Mat<R>& q) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r)
+    if (!(r & (1 << K))) pair_apply(q, x[r], x[r | (1 << K)]);
+}
+template <int K, typename T, typename R>
+__device__ __forceinline__ void blk_real(T* x, const Mat<R>& q) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    if (r & (1 << K)) continue;
+    T& u = x[r];
+    T& v = x[r | (1 << K)];
+    const R ur = u.x, ui = u.y, vr = v.x, vi = v.y;
+    u = T{q.r[0] * ur + q.r[1] * vr, q.r[0] * ui + q.r[1] * vi};
+    v = T{q.r[2] * ur + q.r[3] * vr, q.r[2] * ui + q.r[3] * vi};
+  }
+}
+template <int K, typename T, typename R>
+__device__ __forceinline__ void blk_diag(T* x, const Mat<R>& q) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int e = (r >> K) & 1 ? 3 : 0;
+    const R ar = x[r].x, ai = x[r].y;
+    x[r] = T{q.r[e] * ar - q.i[e] * ai, q.r[e] * ai + q.i[e] * ar};
+  }
+}
+// Controlled X: exchange the pairs whose control bit CR is 1.
+template <int K, int CR, typename T>
+__device__ __forceinline__ void blk_swap(T* x) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    if ((r & (1 << K)) || !((r >> CR) & 1)) continue;
+    const T t = x[r];
+    x[r] = x[r | (1 << K)];
+    x[r | (1 << K)] = t;
   }
 }
 
-// Reverse step on (psi, lambda) in LDS: first this thread's share of
-// Im<lambda|P|psi> for generator P (pauli 1..3, 0 = none), then q (the
-// inverse gate) on both arrays.
-template <typename R, typename T, int B>
-__device__ __forceinline__ double lds_gate2(T* a, T* l, int m, int t, int c, const Mat<R>& q,
-                                            int pauli) {
-  constexpr int V = 2;
-  const uint32_t items = 1u << (m - (c >= 0 ? 2 : 1));
-  const uint32_t s = 1u << t;
-  double g = 0.0;
-  for (uint32_t p0 = threadIdx.x; p0 < items; p0 += B * V) {
-    T x[V], y[V], u[V], w[V];
-    uint32_t i0[V];
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-      i0[v] = pair_base32(p0 + v * B, t, c);
-      if (p0 + v * B < items) {
-        x[v] = a[i0[v]];
-        y[v] = a[i0[v] + s];
-        u[v] = l[i0[v]];
-        w[v] = l[i0[v] + s];
-      }
+// Dispatch on the uniform form, target bit and control bit.  Each branch
+// ends in a distinct empty asm statement: otherwise the optimiser merges
+// similar bodies into one with a runtime register index, which puts the
+// block in scratch memory.
+#define QS_BLK(tag, call) \
+  {                       \
+    call;                 \
+    asm volatile("; blk " tag); \
+  }
+template <typename T, typename R>
+__device__ __forceinline__ void blk_gate_any(T* x, const Mat<R>& q, int rt, int rc, int form) {
+  if (rc < 0) {
+    if (form == kFormReal) {
+      if (rt == 0) QS_BLK("r0", (blk_real<0>(x, q)))
+      else if (rt == 1) QS_BLK("r1", (blk_real<1>(x, q)))
+      else QS_BLK("r2", (blk_real<2>(x, q)))
+    } else if (form == kFormDiag) {
+      if (rt == 0) QS_BLK("d0", (blk_diag<0>(x, q)))
+      else if (rt == 1) QS_BLK("d1", (blk_diag<1>(x, q)))
+      else QS_BLK("d2", (blk_diag<2>(x, q)))
+    } else {
+      if (rt == 0) QS_BLK("u0", (blk_gen<0>(x, q)))
+      else if (rt == 1) QS_BLK("u1", (blk_gen<1>(x, q)))
+      else QS_BLK("u2", (blk_gen<2>(x, q)))
     }
+  } else if (form == kFormSwap) {
+    switch (rt * 4 + rc) {
+      case 1: QS_BLK("s01", (blk_swap<0, 1>(x))) break;
+      case 2: QS_BLK("s02", (blk_swap<0, 2>(x))) break;
+      case 4: QS_BLK("s10", (blk_swap<1, 0>(x))) break;
+      case 6: QS_BLK("s12", (blk_swap<1, 2>(x))) break;
+      case 8: QS_BLK("s20", (blk_swap<2, 0>(x))) break;
+      default: QS_BLK("s21", (blk_swap<2, 1>(x))) break;
+    }
+  } else {
+    if (rt == 0) QS_BLK("c0", (blk_gate<0>(x, q, rc)))
+    else if (rt == 1) QS_BLK("c1", (blk_gate<1>(x, q, rc)))
+    else QS_BLK("c2", (blk_gate<2>(x, q, rc)))
+  }
+}
+// This thread's share of Im<lambda|P|psi> over the pairs of register bit K
+// for P = X (1), Y (2) or Z (3).
+template <int K, int P, typename T>
+__device__ __forceinline__ double blk_grad(const T* x, const T* y) {
+  double g = 0.0;
 #pragma unroll
-    for (int v = 0; v < V; ++v) {
-      if (p0 + v * B < items) {
-        if (pauli)
-          g += pair_grad(pauli, x[v].x, x[v].y, y[v].x, y[v].y, u[v].x, u[v].y, w[v].x, w[v].y);
-        pair_apply(q, x[v], y[v]);
-        pair_apply(q, u[v], w[v]);
-        a[i0[v]] = x[v];
-        a[i0[v] + s] = y[v];
-        l[i0[v]] = u[v];
-        l[i0[v] + s] = w[v];
+  for (int r = 0; r < 8; ++r) {
+    if (r & (1 << K)) continue;
+    const int r1 = r | (1 << K);
+    const double a0r = x[r].x, a0i = x[r].y, a1r = x[r1].x, a1i = x[r1].y;
+    const double l0r = y[r].x, l0i = y[r].y, l1r = y[r1].x, l1i = y[r1].y;
+    // X psi = (a1, a0); Y psi = (-i a1, i a0); Z psi = (a0, -a1)
+    if (P == 1) g += im_conj_mul(l0r, l0i, a1r, a1i) + im_conj_mul(l1r, l1i, a0r, a0i);
+    if (P == 2) g += im_conj_mul(l0r, l0i, a1i, -a1r) + im_conj_mul(l1r, l1i, -a0i, a0r);
+    if (P == 3) g += im_conj_mul(l0r, l0i, a0r, a0i) - im_conj_mul(l1r, l1i, a1r, a1i);
+  }
+  return g;
+}
+template <typename T>
+__device__ __forceinline__ double blk_grad_any(const T* x, const T* y, int pauli, int rt) {
+  double g;
+  if (pauli == 1) {
+    if (rt == 0) QS_BLK("gx0", (g = blk_grad<0, 1>(x, y)))
+    else if (rt == 1) QS_BLK("gx1", (g = blk_grad<1, 1>(x, y)))
+    else QS_BLK("gx2", (g = blk_grad<2, 1>(x, y)))
+  } else if (pauli == 2) {
+    if (rt == 0) QS_BLK("gy0", (g = blk_grad<0, 2>(x, y)))
+    else if (rt == 1) QS_BLK("gy1", (g = blk_grad<1, 2>(x, y)))
+    else QS_BLK("gy2", (g = blk_grad<2, 2>(x, y)))
+  } else {
+    if (rt == 0) QS_BLK("gz0", (g = blk_grad<0, 3>(x, y)))
+    else if (rt == 1) QS_BLK("gz1", (g = blk_grad<1, 3>(x, y)))
+    else QS_BLK("gz2", (g = blk_grad<2, 3>(x, y)))
+  }
+  return g;
+}
+#undef QS_BLK
+
+// One register block on a 2^m-amplitude LDS array (psi; lambda too in the
+// reverse sweep, REV).  Every thread takes 3-qubit sub-cubes in turn; the
+// loop's trip count is uniform, so wave reductions see every lane.
+template <typename R, typename T, int B, bool REV>
+__device__ __forceinline__ void run_block(T* a, T* l, int m, const BBlk& bk, const BRec* recs,
+                                          double* gacc, int wave, int lane) {
+  constexpr int NW = B / 64;
+  const int q0 = bk.q[0], q1 = bk.q[1], q2 = bk.q[2];
+  uint32_t off[8];  // LDS slots of the register offsets (uniform)
+#pragma unroll
+  for (int r = 0; r < 8; ++r)
+    off[r] = Swz<T>::f(((uint32_t)(r & 1) << q0) | ((uint32_t)((r >> 1) & 1) << q1) |
+                       ((uint32_t)((r >> 2) & 1) << q2));
+  const uint32_t nsub = 1u << (m - 3);
+  for (uint32_t s0 = 0; s0 < nsub; s0 += B) {
+    const uint32_t sub = s0 + threadIdx.x;
+    const bool act = sub < nsub;
+    const uint32_t base = Swz<T>::f(ins0(ins0(ins0(sub, q0), q1), q2));
+    T x[8], y[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      x[r] = act ? a[base ^ off[r]] : make_amp<T>(0.0, 0.0);
+      if constexpr (REV) y[r] = act ? l[base ^ off[r]] : make_amp<T>(0.0, 0.0);
+    }
+    for (int k = 0; k < bk.count; ++k) {
+      const int gi = uni(REV ? bk.first + bk.count - 1 - k : bk.first + k);
+      const BRec rec = ldc(recs + gi);
+      const int rt = rec.rt, rc = rec.rc == 0xFF ? -1 : (int)rec.rc;
+      Mat<R> q;
+      rec_mat<R>(rec, REV, q);
+      if constexpr (REV) {
+        if (rec.rot >= 0) {
+          double g = blk_grad_any(x, y, rec.kind - QS_OP_RX + 1, rt);
+          g = wave_sum(g);
+          // no-return atomic: the wave does not wait for the update; one lane
+          // of one wave owns the slot, so the adds land in program order
+          if (lane == 0) atomicAdd(&gacc[rec.rot * NW + wave], g);
+        }
+        blk_gate_any(y, q, rt, rc, rec.form);
+      }
+      blk_gate_any(x, q, rt, rc, rec.form);
+    }
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        a[base ^ off[r]] = x[r];
+        if constexpr (REV) l[base ^ off[r]] = y[r];
       }
     }
   }
-  return g;
 }
 
 // Global index of chunk element k: low bits of k in place, chunk bits
@@ -209,6 +387,54 @@ __device__ __forceinline__ uint32_t chunk_base(uint32_t ch, int low, int K, cons
   return g;
 }
 
+// Chunk transfer between the workspace and LDS for NA arrays (psi; psi and
+// lambda): optionally write the LDS contents back to the chunk at obase,
+// then optionally load the chunk at nbase.  Every thread touches only its
+// own LDS slots, so the write-back and the load need no barrier between
+// them; the loads are issued first so that their latency overlaps the
+// write-back.
+template <typename T, int B, int NA>
+__device__ __forceinline__ void xfer(T* const* lds, T* const* ws, uint32_t M, bool wb,
+                                     uint32_t obase, bool ld, uint32_t nbase, int low, int K,
+                                     const int* hp) {
+  constexpr int UG = NA == 1 ? 8 : 4;
+  for (uint32_t k0 = threadIdx.x; k0 < M; k0 += UG * B) {
+    T v[NA][UG];
+    if (ld) {
+#pragma unroll
+      for (int u = 0; u < UG; ++u) {
+        const uint32_t k = k0 + u * B;
+        if (k < M) {
+          const uint32_t g = chunk_index(k, nbase, low, K, hp);
+#pragma unroll
+          for (int a = 0; a < NA; ++a) v[a][u] = ws[a][g];
+        }
+      }
+    }
+    if (wb) {
+#pragma unroll
+      for (int u = 0; u < UG; ++u) {
+        const uint32_t k = k0 + u * B;
+        if (k < M) {
+          const uint32_t g = chunk_index(k, obase, low, K, hp);
+#pragma unroll
+          for (int a = 0; a < NA; ++a) ws[a][g] = lds[a][Swz<T>::f(k)];
+        }
+      }
+    }
+    if (ld) {
+#pragma unroll
+      for (int u = 0; u < UG; ++u) {
+        const uint32_t k = k0 + u * B;
+        if (k < M) {
+#pragma unroll
+          for (int a = 0; a < NA; ++a) lds[a][Swz<T>::f(k)] = v[a][u];
+        }
+      }
+    }
+  }
+}
+
 template <int B>
 __device__ __forceinline__ double wg_sum(double v, double* red) {
   v = wave_sum(v);
@@ -222,15 +448,6 @@ __device__ __forceinline__ double wg_sum(double v, double* red) {
   return s;
 }
 
-// Copy `count` (<= kRecBlock) records into LDS.
-template <int B>
-__device__ __forceinline__ void stage_recs(BRec* dst, const BRec* src, int count) {
-  constexpr int W = sizeof(BRec) / 16;
-  const uint4* s = (const uint4*)src;
-  uint4* t = (uint4*)dst;
-  for (int k = threadIdx.x; k < count * W; k += B) t[k] = s[k];
-}
-
 // psi = |0...0> over 2^n amplitudes.
 template <typename T, int B>
 __device__ __forceinline__ void init_zero_state(T* psi, int n) {
@@ -239,19 +456,19 @@ __device__ __forceinline__ void init_zero_state(T* psi, int n) {
 
 // lambda = H psi over 2^n amplitudes (terms grouped by x mask); returns this
 // thread's part of Re<psi|lambda>.
-template <typename T, int B>
+template <typename T, int B, typename S>
 __device__ __forceinline__ double apply_h(const T* psi, T* lam, int n, const PauliGroup* groups,
                                           int ngroups, const PauliTerm* terms) {
   double e = 0.0;
   for (uint32_t i = threadIdx.x; i < (1u << n); i += B) {
     double hr = 0.0, hi = 0.0;
     for (int g = 0; g < ngroups; ++g) {
-      const PauliGroup G = groups[g];
+      const PauliGroup G = ldc(groups + g);
       const uint32_t k = i ^ (uint32_t)G.x;
-      const T b = psi[k];
+      const T b = psi[S::f(k)];
       double wr = 0.0, wi = 0.0;
       for (int j = G.first; j < G.first + G.count; ++j) {
-        const PauliTerm P = terms[j];
+        const PauliTerm P = ldc(terms + j);
         const double sgn = (__popc(k & (uint32_t)P.z) & 1) ? -1.0 : 1.0;
         wr += sgn * P.cr;
         wi += sgn * P.ci;
@@ -259,14 +476,14 @@ __device__ __forceinline__ double apply_h(const T* psi, T* lam, int n, const Pau
       hr += wr * (double)b.x - wi * (double)b.y;
       hi += wr * (double)b.y + wi * (double)b.x;
     }
-    lam[i] = make_amp<T>(hr, hi);
-    const T a = psi[i];
+    lam[S::f(i)] = make_amp<T>(hr, hi);
+    const T a = psi[S::f(i)];
     e += (double)a.x * hr + (double)a.y * hi;
   }
   return e;
 }
 
-// Dynamic LDS: psi chunk [2^C], lambda chunk [2^C], gate records [kRecBlock].
+// Dynamic LDS: psi chunk [2^C], lambda chunk [2^C].
 template <typename R, typename T, int B>
 __global__ void __launch_bounds__(B) k_batch(BatchDev d) {
   extern __shared__ uint4 lds_raw[];
@@ -276,7 +493,6 @@ __global__ void __launch_bounds__(B) k_batch(BatchDev d) {
   const int C = d.lds_bits, K = d.khigh, low = C - K;
   T* lpsi = (T*)lds_raw;
   T* llam = lpsi + (1u << C);
-  BRec* lrec = (BRec*)(llam + (1u << C));
   T* wpsi = (T*)(d.ws + (uint64_t)blockIdx.x * d.ws_slot_bytes);
   T* wlam = wpsi + d.state_units;
   double* gacc = (double*)(wlam + d.state_units);  // [rotation][wave]
@@ -289,108 +505,91 @@ __global__ void __launch_bounds__(B) k_batch(BatchDev d) {
     __syncthreads();
     if (qi >= d.ncirc) break;
     const int ci = uni(d.order[qi]);
-    const BCirc cc = d.circ[ci];
+    const BCirc cc = ldc(d.circ + ci);
     const int n = cc.n;
     const bool whole = n <= C;
-    const int m = whole ? n : C;  // bits of the LDS-resident part
+    // bits of the LDS-resident part; states below 3 qubits are padded with
+    // zero amplitudes that no gate touches
+    const int m = whole ? max(n, 3) : C;
     const uint32_t nch = whole ? 1u : 1u << (n - C);
     const uint32_t M = 1u << m;
     const BRec* recs = d.recs + cc.rec_off;
+    const BBlk* blks = d.blks + cc.blk_off;
     const BSeg* segs = d.segs + cc.seg_off;
 
     // 1. |0...0>, gradient slots cleared, forward sweep
-    if (whole) init_zero_state<T, B>(lpsi, n);
+    if (whole) init_zero_state<T, B>(lpsi, m);
     else init_zero_state<T, B>(wpsi, n);
     for (int r = threadIdx.x; r < cc.nrot * NW; r += B) gacc[r] = 0.0;
     __syncthreads();
+    T* const pa[2] = {lpsi, llam};
+    T* const wa[2] = {wpsi, wlam};
     for (int sg = 0; sg < cc.nseg; ++sg) {
-      const BSeg seg = segs[sg];
+      const BSeg seg = ldc(segs + sg);
       int hp[kBatchMaxHigh];
 #pragma unroll
       for (int j = 0; j < kBatchMaxHigh; ++j) hp[j] = seg.hpos[j];
+      uint32_t prev = 0;
       for (uint32_t ch = 0; ch < nch; ++ch) {
         const uint32_t base = whole ? 0u : chunk_base(ch, low, K, hp);
-        if (!whole) {
-          for (uint32_t k = threadIdx.x; k < M; k += B) lpsi[k] = wpsi[chunk_index(k, base, low, K, hp)];
-        }
-        for (int b0 = 0; b0 < seg.count; b0 += kRecBlock) {
-          const int nb = min(kRecBlock, seg.count - b0);
-          stage_recs<B>(lrec, recs + seg.first + b0, nb);
-          __syncthreads();
-          for (int j = 0; j < nb; ++j) {
-            const int hdr = uni(*(const int*)&lrec[j]);
-            const int lt = (hdr >> 8) & 0xFF, lc8 = (hdr >> 16) & 0xFF;
-            Mat<R> q;
-            rec_mat<R>(lrec[j], false, q);
-            lds_gate<R, T, B>(lpsi, m, lt, lc8 == 0xFF ? -1 : lc8, q);
-            __syncthreads();
-          }
-        }
-        if (!whole) {
-          for (uint32_t k = threadIdx.x; k < M; k += B) wpsi[chunk_index(k, base, low, K, hp)] = lpsi[k];
+        if (!whole) xfer<T, B, 1>(pa, wa, M, ch > 0, prev, true, base, low, K, hp);
+        __syncthreads();
+        for (int bi = seg.first; bi < seg.first + seg.count; ++bi) {
+          const BBlk bk = ldc(blks + uni(bi));
+          run_block<R, T, B, false>(lpsi, nullptr, m, bk, recs, gacc, wave, lane);
           __syncthreads();
         }
+        prev = base;
+      }
+      if (!whole) {
+        xfer<T, B, 1>(pa, wa, M, true, prev, false, 0u, low, K, hp);
+        __syncthreads();
       }
     }
 
     // 2. lambda = H psi, E = Re<psi|lambda>
     double e;
-    if (whole)
-      e = apply_h<T, B>(lpsi, llam, n, d.groups + cc.grp_off, cc.ngroups, d.terms);
-    else
-      e = apply_h<T, B>(wpsi, wlam, n, d.groups + cc.grp_off, cc.ngroups, d.terms);
+    if (whole) {
+      for (uint32_t i = (1u << n) + threadIdx.x; i < M; i += B)
+        llam[Swz<T>::f(i)] = make_amp<T>(0.0, 0.0);
+      e = apply_h<T, B, Swz<T>>(lpsi, llam, n, d.groups + cc.grp_off, cc.ngroups, d.terms);
+    } else {
+      e = apply_h<T, B, NoSwz>(wpsi, wlam, n, d.groups + cc.grp_off, cc.ngroups, d.terms);
+    }
     e = wg_sum<B>(e, red);  // its barriers also publish lambda
 
     // 3. reverse sweep, segments and gates in reverse order
     for (int sg = cc.nseg - 1; sg >= 0; --sg) {
-      const BSeg seg = segs[sg];
+      const BSeg seg = ldc(segs + sg);
       int hp[kBatchMaxHigh];
 #pragma unroll
       for (int j = 0; j < kBatchMaxHigh; ++j) hp[j] = seg.hpos[j];
+      uint32_t prev = 0;
       for (uint32_t ch = 0; ch < nch; ++ch) {
         const uint32_t base = whole ? 0u : chunk_base(ch, low, K, hp);
-        if (!whole) {
-          for (uint32_t k = threadIdx.x; k < M; k += B) {
-            const uint32_t gi = chunk_index(k, base, low, K, hp);
-            lpsi[k] = wpsi[gi];
-            llam[k] = wlam[gi];
-          }
-        }
-        for (int b1 = seg.count; b1 > 0; b1 -= kRecBlock) {
-          const int b0 = max(0, b1 - kRecBlock), nb = b1 - b0;
-          stage_recs<B>(lrec, recs + seg.first + b0, nb);
-          __syncthreads();
-          for (int j = nb - 1; j >= 0; --j) {
-            const int hdr = uni(*(const int*)&lrec[j]);
-            const int kind = hdr & 0xFF, lt = (hdr >> 8) & 0xFF, lc8 = (hdr >> 16) & 0xFF;
-            const int rot = uni(lrec[j].rot);
-            Mat<R> q;
-            rec_mat<R>(lrec[j], true, q);
-            const int pauli = rot >= 0 ? kind - QS_OP_RX + 1 : 0;
-            double gg = lds_gate2<R, T, B>(lpsi, llam, m, lt, lc8 == 0xFF ? -1 : lc8, q, pauli);
-            if (rot >= 0) {
-              gg = wave_sum(gg);
-              if (lane == 0) gacc[rot * NW + wave] += gg;
-            }
-            __syncthreads();
-          }
-        }
-        if (!whole) {
-          for (uint32_t k = threadIdx.x; k < M; k += B) {
-            const uint32_t gi = chunk_index(k, base, low, K, hp);
-            wpsi[gi] = lpsi[k];
-            wlam[gi] = llam[k];
-          }
+        if (!whole) xfer<T, B, 2>(pa, wa, M, ch > 0, prev, true, base, low, K, hp);
+        __syncthreads();
+        for (int bi = seg.first + seg.count - 1; bi >= seg.first; --bi) {
+          const BBlk bk = ldc(blks + uni(bi));
+          run_block<R, T, B, true>(lpsi, llam, m, bk, recs, gacc, wave, lane);
           __syncthreads();
         }
+        prev = base;
+      }
+      if (!whole) {
+        xfer<T, B, 2>(pa, wa, M, true, prev, false, 0u, low, K, hp);
+        __syncthreads();
       }
     }
 
-    // 4. outputs; wave slots added in a fixed order
+    // 4. outputs; wave slots added in a fixed order (the workgroup barrier
+    // after the last block orders the adds before these loads, which read the
+    // device cache where the atomics were performed)
     for (int r = threadIdx.x; r < cc.nrot; r += B) {
       double s = 0.0;
 #pragma unroll
-      for (int w = 0; w < NW; ++w) s += gacc[r * NW + w];
+      for (int w = 0; w < NW; ++w)
+        s += __hip_atomic_load(&gacc[r * NW + w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       d.grad_rot[cc.rot_off + r] = s;
     }
     if (threadIdx.x == 0) d.energy[ci] = e;
@@ -414,7 +613,7 @@ Status fail_st(int code, const std::string& msg) {
 }
 
 struct HostOp {
-  uint8_t kind;
+  uint8_t kind, form;
   int8_t target, control;  // control -1: none
   uint32_t qmask;          // qubits acted on
   uint32_t dmask;          // qubits acted on diagonally (a control; a diagonal target)
@@ -447,8 +646,9 @@ struct BatchImpl {
   int sched_C = -1, sched_K = -1;
   const BCirc* circ_dev = nullptr;
   const BRec* recs_dev = nullptr;
+  const BBlk* blks_dev = nullptr;
   const BSeg* segs_dev = nullptr;
-  int64_t nseg_total = 0;
+  int64_t nseg_total = 0, nblk_total = 0;
   void* ws = nullptr;
   size_t ws_bytes = 0;
   double* host_out = nullptr;
@@ -459,27 +659,44 @@ namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// Scan limits of the segment builder: gates looked at past the first
-// unplaced one, and gates left behind, per segment.
+// Scan limits of the segment and block builders: gates looked at past the
+// first unplaced one, and gates left behind, per segment / block.
 constexpr int kSegWindow = 512;
 constexpr int kSegSkip = 96;
+constexpr int kBlkWindow = 128;
+constexpr int kBlkSkip = 24;
+
+// Whether gate h may move ahead of every gate in `later` (each shared qubit
+// acted on diagonally by both).
+bool moves_past(const BatchImpl& b, int64_t o0, const HostOp& h, const std::vector<int>& later) {
+  for (int x : later) {
+    const HostOp& o = b.ops[o0 + x];
+    if ((h.qmask & o.qmask) & ~(h.dmask & o.dmask)) return false;
+  }
+  return true;
+}
 
 // Split circuit c into segments for chunk size 2^C with K higher chunk
-// qubits; append its gate records (execution order, positions local to
-// their segment) and its segments (first = index into `recs`).
+// qubits, and each segment into register blocks.  Appends the circuit's gate
+// records (block order), its blocks (first = record index relative to the
+// circuit's first record) and its segments (first = block index relative to
+// the circuit's first block).
 void segment_circuit(const BatchImpl& b, int c, int C, int K, std::vector<BRec>& recs,
-                     std::vector<BSeg>& segs) {
+                     std::vector<BBlk>& blks, std::vector<BSeg>& segs, int64_t rec0,
+                     int64_t blk0) {
   const int n = b.n[c];
   const int64_t o0 = b.op_off[c];
   const int nops = (int)(b.op_off[c + 1] - o0);
   const bool whole = n <= C;
   const int low = whole ? n : C - K;
+  const int m = whole ? std::max(n, 3) : C;  // bits of the LDS-resident part
   const uint32_t lowmask = (1u << low) - 1u;
+  std::vector<char> used;
+  std::vector<int> blk, later;
   auto emit = [&](const std::vector<int>& gates, std::vector<int>& hs) {
     BSeg s;
     memset(&s, 0, sizeof(s));
-    s.first = (int32_t)recs.size();
-    s.count = (int32_t)gates.size();
+    s.first = (int32_t)((int64_t)blks.size() - blk0);
     if (!whole) {
       for (int q = low; q < n && (int)hs.size() < K; ++q)
         if (std::find(hs.begin(), hs.end(), q) == hs.end()) hs.push_back(q);
@@ -490,17 +707,63 @@ void segment_circuit(const BatchImpl& b, int c, int C, int K, std::vector<BRec>&
       if (whole || q < low) return q;
       return low + (int)(std::find(hs.begin(), hs.end(), q) - hs.begin());
     };
-    for (int g : gates) {
-      const HostOp& h = b.ops[o0 + g];
-      BRec r;
-      memset(&r, 0, sizeof(r));
-      r.kind = h.kind;
-      r.lt = (uint8_t)local(h.target);
-      r.lc = h.control < 0 ? (uint8_t)0xFF : (uint8_t)local(h.control);
-      r.rot = h.rot;
-      memcpy(r.m, &b.mats[(size_t)h.mat * 8], sizeof(r.m));
-      recs.push_back(r);
+    auto lmask = [&](const HostOp& h) -> uint32_t {
+      uint32_t v = 1u << local(h.target);
+      if (h.control >= 0) v |= 1u << local(h.control);
+      return v;
+    };
+    // greedy register blocks over the segment's gate list
+    const int ng = (int)gates.size();
+    used.assign(ng, 0);
+    int first = 0;
+    while (first < ng) {
+      blk.clear();
+      later.clear();
+      uint32_t set = 0;
+      int scanned = 0;
+      for (int i = first; i < ng && scanned < kBlkWindow; ++i) {
+        if (used[i]) continue;
+        ++scanned;
+        const HostOp& h = b.ops[o0 + gates[i]];
+        const uint32_t lm = lmask(h);
+        if (__builtin_popcount(set | lm) <= 3 && moves_past(b, o0, h, later)) {
+          set |= lm;
+          blk.push_back(i);
+          used[i] = 1;
+          continue;
+        }
+        later.push_back(gates[i]);
+        if ((int)later.size() > kBlkSkip) break;
+      }
+      // fill the register set to three bits from the top of the resident part
+      for (int q = m - 1; q >= 0 && __builtin_popcount(set) < 3; --q) set |= 1u << q;
+      BBlk bk;
+      memset(&bk, 0, sizeof(bk));
+      bk.first = (int32_t)((int64_t)recs.size() - rec0);
+      bk.count = (int32_t)blk.size();
+      int pos[32];
+      int j = 0;
+      for (int q = 0; q < m; ++q)
+        if (set >> q & 1u) {
+          pos[q] = j;
+          bk.q[j++] = (uint8_t)q;
+        }
+      for (int i : blk) {
+        const HostOp& h = b.ops[o0 + gates[i]];
+        BRec r;
+        memset(&r, 0, sizeof(r));
+        r.kind = h.kind;
+        r.form = h.form;
+        r.rt = (uint8_t)pos[local(h.target)];
+        r.rc = h.control < 0 ? (uint8_t)0xFF : (uint8_t)pos[local(h.control)];
+        r.rot = h.rot;
+        memcpy(r.m, &b.mats[(size_t)h.mat * 8], sizeof(r.m));
+        recs.push_back(r);
+      }
+      blks.push_back(bk);
+      while (first < ng && used[first]) ++first;
     }
+    s.count = (int32_t)((int64_t)blks.size() - blk0 - s.first);
     segs.push_back(s);
   };
   if (whole) {
@@ -521,16 +784,8 @@ void segment_circuit(const BatchImpl& b, int c, int C, int K, std::vector<BRec>&
       if (placed[g]) continue;
       ++scanned;
       const HostOp& h = b.ops[o0 + g];
-      bool free_to_move = true;
-      for (int x : blocked) {
-        const HostOp& o = b.ops[o0 + x];
-        if ((h.qmask & o.qmask) & ~(h.dmask & o.dmask)) {
-          free_to_move = false;
-          break;
-        }
-      }
       const uint32_t need = h.qmask & ~lowmask;
-      if (free_to_move && __builtin_popcount(hmask | need) <= K) {
+      if (__builtin_popcount(hmask | need) <= K && moves_past(b, o0, h, blocked)) {
         hmask |= need;
         gates.push_back(g);
         placed[g] = 1;
@@ -549,11 +804,13 @@ void segment_circuit(const BatchImpl& b, int c, int C, int K, std::vector<BRec>&
 
 }  // namespace
 
-// Build and upload the schedule (circuits, gate records, segments) for (C, K).
+// Build and upload the schedule (circuits, gate records, register blocks,
+// segments) for (C, K).
 static Status build_schedule(BatchImpl* b, int C, int K) {
   if (b->sched_C == C && b->sched_K == K) return Status::ok();
   std::vector<BCirc> circ(b->ncirc);
   std::vector<BRec> recs;
+  std::vector<BBlk> blks;
   std::vector<BSeg> segs;
   recs.reserve(b->ops.size());
   for (int c = 0; c < b->ncirc; ++c) {
@@ -564,29 +821,46 @@ static Status build_schedule(BatchImpl* b, int C, int K) {
     cc.ngroups = b->ngroups[c];
     cc.nrot = b->nrot[c];
     cc.rec_off = (int64_t)recs.size();
+    cc.blk_off = (int64_t)blks.size();
     cc.grp_off = b->grp_off[c];
     cc.rot_off = b->rot_off[c];
     cc.seg_off = (int64_t)segs.size();
     const size_t seg0 = segs.size();
-    segment_circuit(*b, c, C, K, recs, segs);
-    // segment starts relative to the circuit's first record
-    for (size_t s = seg0; s < segs.size(); ++s) segs[s].first -= (int32_t)cc.rec_off;
+    segment_circuit(*b, c, C, K, recs, blks, segs, cc.rec_off, cc.blk_off);
     cc.nseg = (int32_t)(segs.size() - seg0);
-    // every gate exactly once, every position inside the LDS-resident part
+    cc.nblk = (int32_t)((int64_t)blks.size() - cc.blk_off);
+    // every gate exactly once; blocks tile the records and segments tile the
+    // blocks; register sets inside the LDS-resident part
     if ((int64_t)recs.size() - cc.rec_off != cc.nops)
       return fail_st(QS_EHIP, "batch schedule: gate count mismatch (internal error)");
-    const int m = std::min(cc.n, C);
+    const int m = cc.n <= C ? std::max(cc.n, 3) : C;
+    int64_t next_rec = 0, next_blk = 0;
+    for (size_t s = seg0; s < segs.size(); ++s) {
+      if (segs[s].first != next_blk || segs[s].count < 1)
+        return fail_st(QS_EHIP, "batch schedule: segment layout (internal error)");
+      next_blk += segs[s].count;
+    }
+    if (next_blk != cc.nblk) return fail_st(QS_EHIP, "batch schedule: block count (internal error)");
+    for (int64_t k = cc.blk_off; k < (int64_t)blks.size(); ++k) {
+      const BBlk& bk = blks[k];
+      if (bk.first != next_rec || bk.count < 1 || !(bk.q[0] < bk.q[1] && bk.q[1] < bk.q[2]) ||
+          bk.q[2] >= m)
+        return fail_st(QS_EHIP, "batch schedule: block layout (internal error)");
+      next_rec += bk.count;
+    }
     for (int64_t g = cc.rec_off; g < (int64_t)recs.size(); ++g)
-      if (recs[g].lt >= m || (recs[g].lc != 0xFF && recs[g].lc >= m) || recs[g].lt == recs[g].lc)
-        return fail_st(QS_EHIP, "batch schedule: gate outside its chunk (internal error)");
+      if (recs[g].rt > 2 || (recs[g].rc != 0xFF && recs[g].rc > 2) || recs[g].rt == recs[g].rc)
+        return fail_st(QS_EHIP, "batch schedule: gate outside its block (internal error)");
   }
   const size_t o_circ = 0;
   const size_t o_recs = align256(o_circ + circ.size() * sizeof(BCirc));
-  const size_t o_segs = align256(o_recs + std::max<size_t>(1, recs.size()) * sizeof(BRec));
+  const size_t o_blks = align256(o_recs + std::max<size_t>(1, recs.size()) * sizeof(BRec));
+  const size_t o_segs = align256(o_blks + std::max<size_t>(1, blks.size()) * sizeof(BBlk));
   const size_t total = align256(o_segs + std::max<size_t>(1, segs.size()) * sizeof(BSeg));
   std::vector<char> blob(total, 0);
   memcpy(blob.data() + o_circ, circ.data(), circ.size() * sizeof(BCirc));
   if (!recs.empty()) memcpy(blob.data() + o_recs, recs.data(), recs.size() * sizeof(BRec));
+  if (!blks.empty()) memcpy(blob.data() + o_blks, blks.data(), blks.size() * sizeof(BBlk));
   if (!segs.empty()) memcpy(blob.data() + o_segs, segs.data(), segs.size() * sizeof(BSeg));
   Status st = hip_status(hipStreamSynchronize(b->stream), "batch sync");  // earlier runs may read it
   if (!st.good()) return st;
@@ -607,8 +881,10 @@ static Status build_schedule(BatchImpl* b, int C, int K) {
   char* a = (char*)b->sched;
   b->circ_dev = (const BCirc*)(a + o_circ);
   b->recs_dev = (const BRec*)(a + o_recs);
+  b->blks_dev = (const BBlk*)(a + o_blks);
   b->segs_dev = (const BSeg*)(a + o_segs);
   b->nseg_total = (int64_t)segs.size();
+  b->nblk_total = (int64_t)blks.size();
   b->sched_C = C;
   b->sched_K = K;
   return Status::ok();
@@ -618,6 +894,20 @@ static Status build_schedule(BatchImpl* b, int C, int K) {
 static bool diag_target(const XGate& g) {
   if (g.param >= 0) return g.kind == QS_OP_RZ;
   return g.m[2] == 0.0 && g.m[3] == 0.0 && g.m[4] == 0.0 && g.m[5] == 0.0;
+}
+
+// Register-update form of a gate (the same for every parameter value).
+static uint8_t gate_form(const XGate& g) {
+  if (g.param >= 0) return g.kind == QS_OP_RY ? kFormReal : g.kind == QS_OP_RZ ? kFormDiag : kFormGen;
+  const double* m = g.m;
+  if (g.control >= 0) {
+    const bool x = m[0] == 0.0 && m[1] == 0.0 && m[2] == 1.0 && m[3] == 0.0 && m[4] == 1.0 &&
+                   m[5] == 0.0 && m[6] == 0.0 && m[7] == 0.0;
+    return x ? kFormSwap : kFormGen;
+  }
+  if (diag_target(g)) return kFormDiag;
+  if (m[1] == 0.0 && m[3] == 0.0 && m[5] == 0.0 && m[7] == 0.0) return kFormReal;
+  return kFormGen;
 }
 
 Status batch_create(int dtype, int ncirc, const int32_t* n, const int64_t* op_off,
@@ -658,6 +948,7 @@ Status batch_create(int dtype, int ncirc, const int32_t* n, const int64_t* op_of
     for (const XGate& g : gx) {
       HostOp h;
       h.kind = (uint8_t)g.kind;
+      h.form = gate_form(g);
       h.target = (int8_t)g.target;
       h.control = (int8_t)g.control;
       h.param = g.param;
@@ -795,7 +1086,7 @@ Status batch_run(BatchImpl* b, const qs_batch_tuning* tune, double* energy, doub
   if (b->ncirc == 0) return Status::ok();
   Status st = build_schedule(b, C, K);
   if (!st.good()) return st;
-  const size_t lds = 2 * ((size_t)1 << C) * ab + (size_t)kRecBlock * sizeof(BRec);
+  const size_t lds = 2 * ((size_t)1 << C) * ab;
   const int NW = threads / 64;
   const uint64_t units = b->nmax > C ? 1ull << b->nmax : 0;
   const size_t slot = align256(2 * units * ab + (size_t)b->nrot_max * NW * sizeof(double));
@@ -821,6 +1112,7 @@ Status batch_run(BatchImpl* b, const qs_batch_tuning* tune, double* energy, doub
   memset(&d, 0, sizeof(d));
   d.circ = b->circ_dev;
   d.recs = b->recs_dev;
+  d.blks = b->blks_dev;
   d.segs = b->segs_dev;
   d.groups = b->groups_dev;
   d.terms = b->terms_dev;
