@@ -280,7 +280,8 @@ typedef struct qs_batch_tuning {
                           n <= C qubits stay in LDS, with 2 * 2^C amplitudes
                           <= 128 KiB (0 = 11) */
   int32_t khigh;       /* K: chunk qubits above the C - K lowest, chosen per
-                          gate segment: 2 .. min(8, C - 6) (0 = 4) */
+                          gate segment: 2 .. min(8, C - 6)
+                          (0 = min(5, C - 6)) */
   int32_t wg_per_cu;   /* persistent workgroups per compute unit: 1..8 (0 = 2) */
   int32_t order;       /* 0 = longest circuit first, 1 = input order */
 } qs_batch_tuning;

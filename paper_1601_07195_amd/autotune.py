@@ -31,7 +31,7 @@ SPACE = {
     "wg_per_cu": (1, 2, 3, 4),
     "order": (0, 1),
 }
-DEFAULT = {"threads": 256, "lds_bits": 11, "khigh": 4, "wg_per_cu": 2, "order": 0}
+DEFAULT = {"threads": 256, "lds_bits": 11, "khigh": 5, "wg_per_cu": 2, "order": 0}
 
 
 def valid(t: dict, dtype: int) -> bool:
@@ -80,6 +80,8 @@ def tune(batch: "Q.Batch", repeats: int = 2, cache: str | None = None, log=None)
         for v in values:
             cand = dict(best)
             cand[name] = v
+            if name == "lds_bits":  # keep the chunk qubits valid for the new size
+                cand["khigh"] = min(cand["khigh"], v - 6)
             k = tuple(sorted(cand.items()))
             if k in tried or not valid(cand, batch.dtype):
                 continue

@@ -1066,15 +1066,16 @@ constexpr size_t kBatchWsCap = (size_t)16 << 30;
 
 Status batch_run(BatchImpl* b, const qs_batch_tuning* tune, double* energy, double* grad) {
   const size_t ab = amp_bytes(b->dtype);
-  int threads = 256, wgcu = 2, order = 0, K = 4;
+  int threads = 256, wgcu = 2, order = 0, K = 0;
   int C = 11;
   if (tune) {
     if (tune->threads) threads = tune->threads;
     if (tune->lds_bits) C = tune->lds_bits;
     if (tune->wg_per_cu) wgcu = tune->wg_per_cu;
-    if (tune->khigh) K = tune->khigh;
+    K = tune->khigh;
     order = tune->order;
   }
+  if (K == 0) K = std::min(5, C - 6);
   if (threads != 256 && threads != 512)
     return fail_st(QS_EINVAL, "qs_batch_run: threads must be 256 or 512");
   if (C < 8 || C > 13 || (size_t)2 * ((size_t)1 << C) * ab > (size_t)128 * 1024)
