@@ -175,29 +175,59 @@ __device__ __forceinline__ double reg_grad_any(const T* a, const T* l, int pauli
   }
 }
 
-// Diagonal op on one register tile: amplitude *= d0 or d1 by its target bit.
+// Diagonal op with its target on register bit K: amplitude *= e0 or e1 by
+// its target bit, where its control bit (register creg, uniform) is 1.  PH:
+// the op is a phase (e0 = 1), so the registers whose target bit is 0 are
+// left alone.
+template <int K, bool PH, typename R, int NREG, typename T>
+__device__ __forceinline__ void diag_reg(T* a, R e0r, R e0i, R e1r, R e1i, int creg) {
+  constexpr int RA = 1 << NREG;
+#pragma unroll
+  for (int r = 0; r < RA; ++r) {
+    const bool bit = (r >> K) & 1;
+    if (PH && !bit) continue;
+    const bool c_r = creg < 0 || ((r >> creg) & 1);  // uniform
+    const R er = bit ? e1r : e0r, ei = bit ? e1i : e0i;
+    cscale(a[r], c_r ? er : (R)1, c_r ? ei : (R)0);
+  }
+}
+
+// Diagonal op on one register tile: amplitude *= d0 or d1 by its target bit
+// wherever that bit lives; `on` is false on the lanes whose thread-bit
+// control is 0 (identity there); `phase`: d0 = 1.  Register-bit targets go
+// to bodies specialised for the bit, each ending in a distinct empty asm
+// statement so that the optimiser keeps them apart (merged, they index the
+// tile at run time and spill it).
 template <typename R, int NREG, typename T>
 __device__ __forceinline__ void diag_tile(T* a, R d0r, R d0i, R d1r, R d1i, int tw, int tix,
-                                          int creg, bool on, uint64_t base) {
+                                          int creg, bool on, bool phase, uint64_t base) {
   constexpr int RA = 1 << NREG;
+  const R e0r = on ? d0r : (R)1, e0i = on ? d0i : (R)0;
+  const R e1r = on ? d1r : (R)1, e1i = on ? d1i : (R)0;
   if (tw == kInReg) {
-    // entries per register index: uniform, except for a thread control
-#pragma unroll
-    for (int r = 0; r < RA; ++r) {
-      const bool bit = (r >> tix) & 1;
-      const bool c_r = creg < 0 || ((r >> creg) & 1);
-      R dr = bit ? d1r : d0r, di = bit ? d1i : d0i;
-      dr = c_r ? dr : (R)1;
-      di = c_r ? di : (R)0;
-      dr = on ? dr : (R)1;
-      di = on ? di : (R)0;
-      cscale(a[r], dr, di);
+#define QS_DIAG(KK, PP, tag)                                             \
+  {                                                                      \
+    diag_reg<(KK < NREG ? KK : 0), PP, R, NREG>(a, e0r, e0i, e1r, e1i, creg); \
+    asm volatile("; diag " tag);                                         \
+  }
+    if (phase) {
+      if (tix == 0) QS_DIAG(0, true, "p0")
+      else if (tix == 1) QS_DIAG(1, true, "p1")
+      else if (tix == 2 || NREG == 3) QS_DIAG(2, true, "p2")
+      else QS_DIAG(3, true, "p3")
+    } else {
+      if (tix == 0) QS_DIAG(0, false, "g0")
+      else if (tix == 1) QS_DIAG(1, false, "g1")
+      else if (tix == 2 || NREG == 3) QS_DIAG(2, false, "g2")
+      else QS_DIAG(3, false, "g3")
     }
+#undef QS_DIAG
   } else {
     // target bit fixed for the whole thread (thread bit) or tile (outside)
     const bool bit = (tw == kInThread) ? (bool)((threadIdx.x >> tix) & 1)
                                        : (bool)((base >> tix) & 1);
-    const R tr = on ? (bit ? d1r : d0r) : (R)1, ti = on ? (bit ? d1i : d0i) : (R)0;
+    if (tw == kOutside && phase && !bit) return;  // uniform: a factor of 1
+    const R tr = bit ? e1r : e0r, ti = bit ? e1i : e0i;
 #pragma unroll
     for (int r = 0; r < RA; ++r) {
       const bool c_r = creg < 0 || ((r >> creg) & 1);  // uniform
@@ -231,7 +261,7 @@ __device__ __forceinline__ void run_ops(typename LdsAmp<R>::T* a, typename LdsAm
     nxt = ops[uniform(oi + 1)];
     const FOp* op = &cur;
     const int kw = op->kind, tgt = op->tgt, ctl = op->ctl, aux = op->aux;
-    const int kind = kw & 255, pauli = kw >> 8;
+    const int kind = kw & 255, pauli = (kw >> 8) & 255;
     if (kind == kOpRemap) {
       const FMapDev* mo = maps + uniform(aux);
       const FMapDev* mn = maps + uniform(tgt);
@@ -304,8 +334,9 @@ __device__ __forceinline__ void run_ops(typename LdsAmp<R>::T* a, typename LdsAm
           if ((threadIdx.x & 63) == 0) acc[aux * 4 + (threadIdx.x >> 6)] += g;
         }
       }
-      diag_tile<R, NREG>(a, d0r, d0i, d1r, d1i, tw, tix, creg, on, base);
-      if constexpr (ADJ) diag_tile<R, NREG>(l, d0r, d0i, d1r, d1i, tw, tix, creg, on, base);
+      const bool phase = (kw >> 16) & 1;
+      diag_tile<R, NREG>(a, d0r, d0i, d1r, d1i, tw, tix, creg, on, phase, base);
+      if constexpr (ADJ) diag_tile<R, NREG>(l, d0r, d0i, d1r, d1i, tw, tix, creg, on, phase, base);
     }
   }
 }
@@ -479,6 +510,11 @@ static Status upload_plan(StateImpl* s, const Plan& plan, const FuseGeom& G, con
   const size_t ob = (plan.ops.size() + 1) * sizeof(FOp), mb = md.size() * sizeof(FMapDev);
   std::vector<char> blob(ob + mb, 0);
   memcpy(blob.data(), plan.ops.data(), plan.ops.size() * sizeof(FOp));
+  // diagonal ops with d0 = 1 (phases) leave target-bit-0 amplitudes alone
+  FOp* fo = (FOp*)blob.data();
+  for (size_t i = 0; i < plan.ops.size(); ++i)
+    if ((fo[i].kind & 255) == kOpDiag && fo[i].m[0] == 1.0 && fo[i].m[1] == 0.0)
+      fo[i].kind |= kDiagPhase;
   memcpy(blob.data() + ob, md.data(), mb);
   Status st = upload_table(s, blob.data(), blob.size());
   if (!st.good()) return st;

@@ -135,6 +135,9 @@ enum SpecWhere { kInReg = 0, kInThread = 1, kOutside = 2, kNoBit = 3 };
 inline int32_t make_spec(int where, int index) { return (where << 8) | index; }
 
 enum FOpKind { kOpRemap = 0, kOpU = 1, kOpDiag = 2 };
+// FOp::kind bits 8..15: the Pauli generator of a gradient op; bit 16 on a
+// diagonal op: d0 = 1 (a phase), set when the plan is uploaded.
+constexpr int32_t kDiagPhase = 1 << 16;
 struct FOp {
   int32_t kind;
   int32_t tgt;   // kOpU: register bit; kOpDiag: spec of the target; kOpRemap: new FMap index
