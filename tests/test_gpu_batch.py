@@ -169,3 +169,68 @@ def test_autotune_picks_a_valid_shape(Q):
     e0, g0 = b.run_flat()
     e, g = b.run_flat(A.fields(t))
     assert np.abs(e - e0).max() <= 1e-12 and np.abs(g - g0).max() <= 1e-11
+
+
+def forms_items(seed, widths):
+    """Every register-update form of the batch kernel: X (real), H (real),
+    CNOT in both directions (controlled exchange), CZ and controlled phases
+    (controlled diagonal, general path), fixed diagonal and real gates,
+    controlled Haar gates, RX (general), RY (real) and RZ (diagonal)
+    rotations, with qubits anywhere in the state."""
+    items = []
+    for j, n in enumerate(widths):
+        rng = np.random.default_rng(seed + j)
+        parts = []
+        npar = 3 * n
+        for _ in range(4 * n):
+            q = int(rng.integers(n))
+            c, t = (int(v) for v in rng.choice(n, 2, replace=False)) if n > 1 else (0, 0)
+            r = int(rng.integers(10))
+            if r == 0:
+                parts.append(C.op_u(q, C.X_GATE))
+            elif r == 1:
+                parts.append(C.op_u(q, C.H_GATE))
+            elif r == 2 and n > 1:
+                parts.append(C.op_cu(c, t, C.X_GATE))
+            elif r == 3 and n > 1:
+                parts.append(C.op_cu(c, t, np.diag([1.0, -1.0])))
+            elif r == 4 and n > 1:
+                parts.append(C.op_cu(c, t, np.diag([1.0, np.exp(1j * rng.uniform(0, 6))])))
+            elif r == 5:
+                parts.append(C.op_u(q, np.diag(np.exp(1j * rng.uniform(0, 6, 2)))))
+            elif r == 6 and n > 1:
+                parts.append(C.op_cu(c, t, C.haar_unitary(rng)))
+            else:
+                kind = [C.OP_RX, C.OP_RY, C.OP_RZ][r % 3]
+                parts.append(C.op_rot(kind, q, int(rng.integers(npar))))
+        ops = np.concatenate(parts)
+        theta = rng.uniform(0, 2 * np.pi, npar)
+        ham = C.random_pauli_sum(n, 7, rng)
+        items.append((n, ops, theta, ham.codes, ham.coeff))
+    return items
+
+
+@pytest.mark.parametrize("tuning", [None, {"lds_bits": 10, "khigh": 3, "threads": 512},
+                                    {"lds_bits": 8, "khigh": 2}])
+def test_batch_gate_forms_vs_oracle(Q, tuning):
+    """States in LDS (n <= C, including 1 and 2 qubits padded to a 3-qubit
+    register block) and chunked states (n > C)."""
+    items = forms_items(7700, [1, 2, 3, 5, 8, 9, 11, 12])
+    b = Q.Batch(items, Q.QS_C128)
+    e, g = b.run(tuning)
+    for c, (n, ops, theta, codes, coeff) in enumerate(items):
+        assert abs(e[c] - O.energy(ops, n, theta, codes, coeff)) <= 1e-12, c
+        rg = O.grad_param_shift(ops, n, theta, codes, coeff)
+        assert np.abs(g[c] - rg).max() <= 1e-10, c
+
+
+def test_batch_widest_states_vs_unbatched(Q):
+    """The widest batched states (up to QS_BATCH_MAX_QUBITS) run chunked with
+    the most chunks per segment; checked against the unbatched adjoint."""
+    items = forms_items(7800, [20, Q.QS_BATCH_MAX_QUBITS])
+    b = Q.Batch(items, Q.QS_C128)
+    e, g = b.run()
+    for c, item in enumerate(items):
+        re, rg = unbatched(Q, item, Q.QS_C128)
+        assert abs(e[c] - re) <= 1e-11 * max(1.0, abs(re)), c
+        assert np.abs(g[c] - rg).max() <= 1e-10, c
