@@ -107,6 +107,77 @@ k_probabilities(const T* __restrict__ a, int n, uint64_t nchunks, double* __rest
   }
 }
 
+// complex64: 16-byte units of two amplitudes (bit 0 inside the unit), chunks
+// of 2^13 amplitudes: in chunk ch lane t reads unit u = ch*4096 + r*256 + t,
+// amplitudes 2u and 2u + 1.  Index bit 0 is the unit half, bits 1..8 the
+// lane, bits 9..12 r, bits >= 13 the chunk number.
+template <bool FULL>
+__global__ void __launch_bounds__(kBlock)
+k_probabilities_c64(const f4* __restrict__ a, int n, uint64_t nchunks, double* __restrict__ part,
+                    double* __restrict__ full) {
+  constexpr int CL = kProbChunkLog + 1;
+  const uint64_t NU = 1ull << (n - 1);  // units (n >= 1)
+  double tot = 0.0, b0 = 0.0, mid[4] = {0.0, 0.0, 0.0, 0.0};
+  double hi[kMaxQubits - CL];
+#pragma unroll
+  for (int b = 0; b < kMaxQubits - CL; ++b) hi[b] = 0.0;
+
+  for (uint64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    const uint64_t base = ch << (CL - 1);
+    double s = 0.0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const uint64_t u = base + (uint64_t)r * kBlock + threadIdx.x;
+      double p = 0.0;
+      if (u < NU) {
+        const f4 v = a[u];
+        const double p0 = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+        const double p1 = (double)v.z * (double)v.z + (double)v.w * (double)v.w;
+        if (FULL) {  // full is only 8-byte aligned
+          full[2 * u] = p0;
+          full[2 * u + 1] = p1;
+        }
+        b0 += p1;
+        p = p0 + p1;
+      }
+      s += p;
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        if ((r >> b) & 1) mid[b] += p;
+    }
+    tot += s;
+#pragma unroll
+    for (int b = 0; b < kMaxQubits - CL; ++b)
+      if ((ch >> b) & 1) hi[b] += s;
+  }
+  __shared__ double wsum[kMaxQubits + 1][kBlock / 64];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < kMaxQubits; ++k) {
+    double v;
+    if (k == 0) v = b0;
+    else if (k < 9) v = ((threadIdx.x >> (k - 1)) & 1) ? tot : 0.0;
+    else if (k < CL) v = mid[k - 9];
+    else v = hi[k - CL];
+    v = wave_sum(v);
+    if (lane == 0) wsum[k][w] = v;
+  }
+  {
+    const double t = wave_sum(tot);
+    if (lane == 0) wsum[kMaxQubits][w] = t;
+  }
+  __syncthreads();
+  double* row = part + (size_t)blockIdx.x * (n + 1);
+  const int k = threadIdx.x;
+  if (k <= n) {
+    const int src = (k == n) ? kMaxQubits : k;
+    double v = 0.0;
+#pragma unroll
+    for (int j = 0; j < kBlock / 64; ++j) v += wsum[src][j];
+    row[k] = v;
+  }
+}
+
 // ------------------------------------------------------------ Pauli sums
 // For a Pauli string with masks (x, z) and n_Y = popcount(x & z) factors Y:
 //   P|k> = i^(n_Y) (-1)^popcount(k & z) |k ^ x>        (Y = i X Z)
@@ -217,7 +288,8 @@ static unsigned reduce_grid(uint64_t items, int per_block) {
 Status launch_probabilities(StateImpl* s, double* p1_host, double* norm2_host, double* full_dev) {
   const int n = s->n;
   const uint64_t N = 1ull << n;
-  const uint64_t nchunks = (N + (1ull << kProbChunkLog) - 1) >> kProbChunkLog;
+  const int cl = s->dtype == QS_C128 ? kProbChunkLog : kProbChunkLog + 1;  // log2 amplitudes per chunk
+  const uint64_t nchunks = (N + (1ull << cl) - 1) >> cl;
   const unsigned grid = (unsigned)std::min<uint64_t>(nchunks, kReduceGrid);
   const size_t ncols = (size_t)n + 1;
   Status st = ensure_dev(s, s->red, (grid * ncols + ncols) * sizeof(double));
@@ -233,11 +305,11 @@ Status launch_probabilities(StateImpl* s, double* p1_host, double* norm2_host, d
                          (const d2*)s->ptr, n, nchunks, part, nullptr);
   } else {
     if (full_dev)
-      hipLaunchKernelGGL((k_probabilities<f2, true>), dim3(grid), dim3(kBlock), 0, s->stream,
-                         (const f2*)s->ptr, n, nchunks, part, full_dev);
+      hipLaunchKernelGGL((k_probabilities_c64<true>), dim3(grid), dim3(kBlock), 0, s->stream,
+                         (const f4*)s->ptr, n, nchunks, part, full_dev);
     else
-      hipLaunchKernelGGL((k_probabilities<f2, false>), dim3(grid), dim3(kBlock), 0, s->stream,
-                         (const f2*)s->ptr, n, nchunks, part, nullptr);
+      hipLaunchKernelGGL((k_probabilities_c64<false>), dim3(grid), dim3(kBlock), 0, s->stream,
+                         (const f4*)s->ptr, n, nchunks, part, nullptr);
   }
   st = last_launch("probabilities");
   if (!st.good()) return st;
