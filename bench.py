@@ -21,9 +21,11 @@ Extra objects on the same JSON line: `roofline` for the dominant kernel
 (timed with HIP events on the stream the kernels run on), `cpu_baseline`
 (the CPU oracle on a bounded sample), `stream_copy` (measured B_mem) and
 per-category detail.  Further sections (each skippable): n=33 / n=34 large
-states, adjoint vs parameter-shift gradients (n=20, n=28), and the batched
-persistent launch (4096 small ansatz circuits, energy + gradient).  One GPU
-only: --gpus above 1 exits with a message.
+states, the QFT / IQFT fused-vs-unfused sweep (n = 18..31, effective
+bandwidth in the paper's sense), adjoint vs parameter-shift gradients
+(n=20, n=28), and the batched persistent launch (4096 small ansatz
+circuits, energy + gradient).  One GPU only: --gpus above 1 exits with a
+message.
 """
 from __future__ import annotations
 
@@ -54,6 +56,8 @@ def parse():
     ap.add_argument("--no-large", action="store_true", help="skip the n=33/34 (128 GiB) section")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint vs parameter-shift section")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-launch section")
+    ap.add_argument("--no-qft", action="store_true",
+                    help="skip the QFT/IQFT fused-vs-unfused sweep (n = 18..31)")
     ap.add_argument("--ps-pairs", type=int, default=8,
                     help="parameter-shift pairs timed at n=28 (extrapolated to all 2P sweeps)")
     ap.add_argument("--cpu-n", type=int, default=0, help="qubits of the CPU-oracle sample (0 = auto)")
@@ -200,6 +204,9 @@ def large_section(Q, C, np, torch):
         info, _, _ = Q.qs_plan(n, dtype, circ.ops)
         pergate = sum((S if op["kind"] == C.OP_CU else 2 * S) for op in circ.ops)
         tc = timed(lambda: st.run(circ.ops), stream, 1)
+        qft = C.qft_circuit(n)
+        qinfo, _, _ = Q.qs_plan(n, dtype, qft.ops)
+        tq = timed(lambda: st.run(qft.ops), stream, 1)
         out[f"n{n}_{name}"] = {
             "state_bytes": S,
             "one_qubit_GBps_by_target": one,
@@ -209,9 +216,49 @@ def large_section(Q, C, np, torch):
                         "hbm_GBps": round(info["hbm_bytes"] / tc / 1e9, 1),
                         "effective_GBps_paper_def": round(pergate / tc / 1e9, 1),
                         "paper_qft_only_s": {"33": 245.0, "34": 297.4}[str(n)]},
+            "qft_only": {"gates": len(qft), "passes": qinfo["passes"], "s": round(tq, 4),
+                         "effective_GBps_paper_def": round(
+                             sum((S if op["kind"] == C.OP_CU else 2 * S) for op in qft.ops) / tq / 1e9, 1)},
         }
         del st
         torch.cuda.empty_cache()
+    return out
+
+
+def qft_section(Q, C, np, torch):
+    """QFT and IQFT on all qubits, run fused (one HBM round trip per pass of
+    gates) and with one streaming pass per gate, over a sweep of widths: the
+    GPU analogue of the paper's fused-vs-unfused comparison (Sec. 5.5).
+    Effective bandwidth is the paper's definition: the per-gate algorithmic
+    bytes (Table 2: 2S per 1q gate, S per controlled gate) over the time."""
+    out = {}
+    stream = torch.cuda.current_stream()
+    for name, dtype, b, ns in (("c128", Q.QS_C128, 16, (18, 20, 22, 24, 26, 28, 30)),
+                               ("c64", Q.QS_C64, 8, (19, 21, 23, 25, 27, 29, 31))):
+        rows = {}
+        for n in ns:
+            S = (1 << n) * b
+            st = Q.State(n, dtype, stream=stream)
+            rec = {}
+            for cname, circ in (("qft", C.qft_circuit(n)), ("iqft", C.iqft_circuit(n))):
+                pergate = sum((S if op["kind"] == C.OP_CU else 2 * S) for op in circ.ops)
+                info, _, _ = Q.qs_plan(n, dtype, circ.ops)
+                reps = 3 if n <= 24 else 1
+                tf = timed(lambda: st.run(circ.ops), stream, reps)
+                tu = timed(lambda: st.run(circ.ops, fuse=False), stream, reps)
+                rec[cname] = {
+                    "gates": len(circ), "passes_fused": info["passes"],
+                    "fused_s": round(tf, 5), "unfused_s": round(tu, 5),
+                    "fused_effective_GBps": round(pergate / tf / 1e9, 1),
+                    "unfused_effective_GBps": round(pergate / tu / 1e9, 1),
+                    "fused_hbm_GBps": round(info["hbm_bytes"] / tf / 1e9, 1),
+                    "speedup": round(tu / tf, 2),
+                }
+            rows[str(n)] = rec
+            del st
+            torch.cuda.empty_cache()
+        log(f"[bench] qft sweep {name}: n={ns[0]}..{ns[-1]} done")
+        out[name] = rows
     return out
 
 
@@ -513,6 +560,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_large:
         line["large_states"] = large_section(Q, C, np, torch)
+    if not args.no_qft:
+        line["qft_fused_vs_unfused"] = qft_section(Q, C, np, torch)
     if not args.no_adjoint:
         line["adjoint_vs_param_shift"] = adjoint_section(Q, C, np, torch, args.ps_pairs)
     if not args.no_batch:

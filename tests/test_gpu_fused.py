@@ -114,3 +114,27 @@ def test_fused_u_then_udagger(Q):
     st = to_gpu_state(Q, psi, Q.QS_C128)
     st.run(circ.ops).run(inv)
     assert np.abs(st.numpy() - psi).max() <= 1e-12
+
+
+@pytest.mark.parametrize("fused", [True, False])
+@pytest.mark.parametrize("name,n", [("c128", 13), ("c128", 18), ("c64", 15)])
+def test_qft_iqft_fused_and_unfused(Q, name, n, fused):
+    """The QFT/IQFT pair of the fused-vs-unfused sweep: QFT of a random state
+    against the oracle, then the IQFT returns the input; both with fusion and
+    with one streaming pass per gate."""
+    flags = 0 if fused else Q.QS_RUN_NO_FUSION
+    psi = random_state(n, np.random.default_rng(900 + n))
+    st = to_gpu_state(Q, psi, dt(Q, name))
+    held = st.numpy()
+    qft = C.qft_circuit(n).ops
+    st.run(qft, fuse=fused)
+    ref = O.run(qft, n, psi=held.astype(np.complex128))
+    ngates = len(qft)
+    assert np.abs(st.numpy() - ref).max() <= bound(name, ngates)
+    st.run(C.iqft_circuit(n).ops, fuse=fused)
+    assert np.abs(st.numpy() - held).max() <= bound(name, 2 * ngates)
+    info, _, _ = Q.qs_plan(n, dt(Q, name), qft, flags=flags)
+    if fused:
+        assert info["passes"] < ngates
+    else:
+        assert info["passes"] == ngates and info["fused"] == 0
