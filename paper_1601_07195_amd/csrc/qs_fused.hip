@@ -247,7 +247,7 @@ __device__ __forceinline__ void diag_tile(T* a, R d0r, R d0i, R d1r, R d1i, int 
 // gradient slot first add Im<lambda|P|psi> (P = the rotation's generator,
 // X/Y on register pairs, Z by the sign of the target bit) to the wave's LDS
 // accumulator of that slot.
-template <typename R, int NREG, bool ADJ>
+template <typename R, int NREG, bool ADJ, bool RUNS = false>
 __device__ __forceinline__ void run_ops(typename LdsAmp<R>::T* a, typename LdsAmp<R>::T* l,
                                         typename LdsAmp<R>::T* lds, const FOp* __restrict__ ops,
                                         int nops, const FMapDev* __restrict__ maps,
@@ -270,6 +270,26 @@ __device__ __forceinline__ void run_ops(typename LdsAmp<R>::T* a, typename LdsAm
       const int tn = LdsAmp<R>::swz(thr_tile_off(mn->thr_pack)) * ES;
       remap_tile<R, NREG>(a, lds, to, mo, tn, mn);
       if constexpr (ADJ) remap_tile<R, NREG>(l, lds, to, mo, tn, mn);
+      continue;
+    }
+    if (RUNS && kind == kOpPhaseRun) {  // forward passes that hold runs only
+      // the product of the run's phases, per lane: entry e contributes its
+      // d1 where its control (none, a thread bit or a bit outside the tile)
+      // is 1; then the target-bit-1 amplitudes are scaled once
+      R pr = (R)1, pi = (R)0;
+      for (int e = 1; e <= aux; ++e) {
+        const FOp* en = ops + uniform(oi + e);
+        const int ec = en->ctl, ew = ec >> 8, eb = ec & 255;
+        const bool eon = ew == kNoBit || (ew == kInThread ? (bool)((threadIdx.x >> eb) & 1)
+                                                          : (bool)((base >> eb) & 1));
+        const R dr = eon ? (R)en->m[6] : (R)1, di = eon ? (R)en->m[7] : (R)0;
+        const R t = pr * dr - pi * di;
+        pi = pr * di + pi * dr;
+        pr = t;
+      }
+      diag_tile<R, NREG>(a, (R)1, (R)0, pr, pi, kInReg, tgt & 255, -1, true, true, base);
+      oi += aux;
+      nxt = ops[uniform(oi + 1)];
       continue;
     }
     const int cw = ctl >> 8, ci = ctl & 255;
@@ -353,7 +373,9 @@ __device__ __forceinline__ uint64_t tile_base(uint64_t tile, const FusedArgs& A)
 // stores of different workgroups better than a persistent loop here).
 
 // complex128: one d2 per amplitude.
-template <int NREG>
+// RUNS: the pass holds phase runs (a separate instance, so that passes
+// without them keep the smaller register budget and schedule).
+template <int NREG, bool RUNS>
 __global__ void __launch_bounds__(kFuseBlock)
 k_fused_c128(d2* __restrict__ a, FusedArgs A, const FOp* __restrict__ ops,
              const FMapDev* __restrict__ maps) {
@@ -365,7 +387,7 @@ k_fused_c128(d2* __restrict__ a, FusedArgs A, const FOp* __restrict__ ops,
     const uint64_t base = tile_base(tile, A);
 #pragma unroll
     for (int r = 0; r < RA; ++r) t[r] = gload<true>(a + (base | tl | reg_global_off<NREG>(A.ld_reg, r)));
-    run_ops<double, NREG, false>(t, nullptr, lds, ops, A.nops, maps, base, nullptr);
+    run_ops<double, NREG, false, RUNS>(t, nullptr, lds, ops, A.nops, maps, base, nullptr);
 #pragma unroll
     for (int r = 0; r < RA; ++r) gstore<true>(a + (base | ts | reg_global_off<NREG>(A.st_reg, r)), t[r]);
   }
@@ -373,7 +395,7 @@ k_fused_c128(d2* __restrict__ a, FusedArgs A, const FOp* __restrict__ ops,
 
 // complex64: 16-byte units of two amplitudes; register bit 0 is qubit 0 at
 // load and store, so registers (2u, 2u + 1) form one unit.
-template <int NREG>
+template <int NREG, bool RUNS>
 __global__ void __launch_bounds__(kFuseBlock)
 k_fused_c64(f4* __restrict__ a, FusedArgs A, const FOp* __restrict__ ops,
             const FMapDev* __restrict__ maps) {
@@ -389,7 +411,7 @@ k_fused_c64(f4* __restrict__ a, FusedArgs A, const FOp* __restrict__ ops,
       t[r] = f2{v.x, v.y};
       t[r + 1] = f2{v.z, v.w};
     }
-    run_ops<float, NREG, false>(t, nullptr, lds, ops, A.nops, maps, base, nullptr);
+    run_ops<float, NREG, false, RUNS>(t, nullptr, lds, ops, A.nops, maps, base, nullptr);
 #pragma unroll
     for (int r = 0; r < RA; r += 2)
       gstore<true>(a + ((base | ts | reg_global_off<NREG>(A.st_reg, r)) >> 1),
@@ -554,12 +576,23 @@ Status run_gates(StateImpl* s, const std::vector<XGate>& gates, int flags) {
     } else {
       const FusedArgs A = pass_args(s, plan, p, G);
       const unsigned grid = (unsigned)std::min<uint64_t>(A.ntiles, (1ull << 31) / kFuseBlock);
-      if (s->dtype == QS_C128)
-        hipLaunchKernelGGL((k_fused_c128<3>), dim3(grid), dim3(kFuseBlock), 0, s->stream,
-                           (d2*)s->ptr, A, dops + p.op_first, dmaps);
-      else
-        hipLaunchKernelGGL((k_fused_c64<4>), dim3(grid), dim3(kFuseBlock), 0, s->stream,
-                           (f4*)s->ptr, A, dops + p.op_first, dmaps);
+      bool runs = false;
+      for (int i = p.op_first; i < p.op_first + p.nops; ++i) runs |= plan.ops[i].kind == kOpPhaseRun;
+      if (s->dtype == QS_C128) {
+        if (runs)
+          hipLaunchKernelGGL((k_fused_c128<3, true>), dim3(grid), dim3(kFuseBlock), 0, s->stream,
+                             (d2*)s->ptr, A, dops + p.op_first, dmaps);
+        else
+          hipLaunchKernelGGL((k_fused_c128<3, false>), dim3(grid), dim3(kFuseBlock), 0, s->stream,
+                             (d2*)s->ptr, A, dops + p.op_first, dmaps);
+      } else {
+        if (runs)
+          hipLaunchKernelGGL((k_fused_c64<4, true>), dim3(grid), dim3(kFuseBlock), 0, s->stream,
+                             (f4*)s->ptr, A, dops + p.op_first, dmaps);
+        else
+          hipLaunchKernelGGL((k_fused_c64<4, false>), dim3(grid), dim3(kFuseBlock), 0, s->stream,
+                             (f4*)s->ptr, A, dops + p.op_first, dmaps);
+      }
       st = last_launch("fused pass");
     }
     if (!st.good()) return st;

@@ -134,7 +134,12 @@ struct FMap {
 enum SpecWhere { kInReg = 0, kInThread = 1, kOutside = 2, kNoBit = 3 };
 inline int32_t make_spec(int where, int index) { return (where << 8) | index; }
 
-enum FOpKind { kOpRemap = 0, kOpU = 1, kOpDiag = 2 };
+// kOpPhaseRun: `aux` consecutive phase entries follow (kOpPhaseEntry, each a
+// diagonal op with d0 = 1, its control spec in `ctl` and no register
+// control); all share the run's target `tgt`, a register bit.  The kernel
+// multiplies the entries' d1 into one per-lane factor and scales the
+// target-bit-1 amplitudes once.
+enum FOpKind { kOpRemap = 0, kOpU = 1, kOpDiag = 2, kOpPhaseRun = 3, kOpPhaseEntry = 4 };
 // FOp::kind bits 8..15: the Pauli generator of a gradient op; bit 16 on a
 // diagonal op: d0 = 1 (a phase), set when the plan is uploaded.
 constexpr int32_t kDiagPhase = 1 << 16;

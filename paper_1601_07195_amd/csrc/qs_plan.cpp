@@ -422,6 +422,58 @@ void plan_gates(int n, int dtype, const std::vector<XGate>& gates, bool fuse, Pl
       cur = load;
     }
     p.map_store = (int)out->maps.size() - 1;
+    // ---- phase runs: consecutive phase ops (d0 = 1, no gradient slot, no
+    // register control) on the same register target become one run header
+    // followed by their entries (diagonal ops commute, so the product is
+    // exact up to rounding).  Forward passes only: the adjoint kernels have
+    // no registers to spare for it.
+    if (!grad) {
+      auto member = [&](const FOp& o) {
+        return (o.kind & 255) == kOpDiag && o.aux < 0 && o.m[0] == 1.0 && o.m[1] == 0.0 &&
+               (o.tgt >> 8) == kInReg && (o.ctl >> 8) != kInReg;
+      };
+      std::vector<FOp> nops;
+      std::vector<OpMeta> nmeta;
+      size_t i = (size_t)p.op_first;
+      while (i < out->ops.size()) {
+        size_t j = i;
+        if (member(out->ops[i]))
+          while (j + 1 < out->ops.size() && member(out->ops[j + 1]) &&
+                 out->ops[j + 1].tgt == out->ops[i].tgt)
+            ++j;
+        if (j > i) {
+          FOp h;
+          std::memset(&h, 0, sizeof(h));
+          h.kind = kOpPhaseRun;
+          h.tgt = out->ops[i].tgt;
+          h.ctl = make_spec(kNoBit, 0);
+          h.aux = (int)(j - i + 1);
+          nops.push_back(h);
+          OpMeta hm = meta[i];
+          hm.remap = true;  // never a merge target
+          hm.mergeable = false;
+          nmeta.push_back(hm);
+          for (size_t k = i; k <= j; ++k) {
+            FOp e = out->ops[k];
+            e.kind = kOpPhaseEntry;
+            nops.push_back(e);
+            OpMeta em = meta[k];
+            em.remap = true;
+            em.mergeable = false;
+            nmeta.push_back(em);
+          }
+          i = j + 1;
+          continue;
+        }
+        nops.push_back(out->ops[i]);
+        nmeta.push_back(meta[i]);
+        ++i;
+      }
+      out->ops.resize((size_t)p.op_first);
+      meta.resize((size_t)p.op_first);
+      out->ops.insert(out->ops.end(), nops.begin(), nops.end());
+      meta.insert(meta.end(), nmeta.begin(), nmeta.end());
+    }
     p.nops = (int)out->ops.size() - p.op_first;
     out->passes.push_back(p);
   }
