@@ -390,7 +390,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
-              f"(this build has no multi-GPU path).", file=sys.stderr)
+              f"(the simulator holds the whole state on one GPU).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
