@@ -43,6 +43,7 @@ def lib():
         L.oracle_init_basis.argtypes = [vp, i, u64]
         L.oracle_apply_1q.argtypes = [vp, i, i, vp]
         L.oracle_apply_cu.argtypes = [vp, i, i, i, vp]
+        L.oracle_apply_kq.argtypes = [vp, i, i, vp, vp]
         L.oracle_probabilities.argtypes = [vp, i, vp, vp, vp]
         L.oracle_inner.argtypes = [vp, vp, i, _dp, _dp]
         L.oracle_apply_pauli_string.argtypes = [vp, i, vp, vp]
@@ -104,6 +105,24 @@ def apply_cu(psi: np.ndarray, n: int, c: int, t: int, q) -> np.ndarray:
         raise ValueError("bad control/target")
     m = _mat8(q)
     lib().oracle_apply_cu(_ptr(_state(psi, n)), n, c, t, _ptr(m))
+    return psi
+
+
+KQ_MAX = 5  # largest k the oracle's k-qubit gate takes (groups of 32 amplitudes)
+
+
+def apply_kq(psi: np.ndarray, n: int, targets, u) -> np.ndarray:
+    """In place: the 2^k x 2^k matrix u on the qubits `targets` (bit j of u's
+    index is qubit targets[j])."""
+    t = np.ascontiguousarray(targets, dtype=np.int32)
+    k = len(t)
+    if not 1 <= k <= KQ_MAX or len(set(t.tolist())) != k or t.min() < 0 or t.max() >= n:
+        raise ValueError("bad targets")
+    m = np.asarray(u, dtype=np.complex128)
+    if m.shape != (1 << k, 1 << k):
+        raise ValueError("u must be 2^k x 2^k")
+    flat = np.ascontiguousarray(m).view(np.float64).copy()
+    lib().oracle_apply_kq(_ptr(_state(psi, n)), n, k, _ptr(t), _ptr(flat))
     return psi
 
 

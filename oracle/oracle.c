@@ -117,6 +117,37 @@ void oracle_apply_cu(cplx* a, int n, int c, int t, const double* q) {
 }
 
 /*
+ * A gate on a block of k qubits: u is the 2^k x 2^k matrix, row-major, each
+ * entry (re, im); targets[j] is the qubit that bit j of u's row and column
+ * index refers to.  The same reading of Eq. (2) for k qubits: every group
+ * of 2^k amplitudes whose indices differ only in the target bits, listed in
+ * the order of that k-bit index, is replaced by u times the group.
+ */
+void oracle_apply_kq(cplx* a, int n, int k, const int* targets, const double* u) {
+  const int64_t N = (int64_t)1 << n, K = (int64_t)1 << k;
+  int64_t tmask = 0;
+  for (int j = 0; j < k; j++) tmask |= (int64_t)1 << targets[j];
+#pragma omp parallel for num_threads(g_threads) if (g_threads > 1) schedule(static)
+  for (int64_t i = 0; i < N; i++) {
+    if (i & tmask) continue; /* i is the group's member with every target bit 0 */
+    int64_t idx[32];
+    cplx v[32];
+    for (int64_t r = 0; r < K; r++) {
+      int64_t x = i;
+      for (int j = 0; j < k; j++)
+        if ((r >> j) & 1) x |= (int64_t)1 << targets[j];
+      idx[r] = x;
+      v[r] = a[x];
+    }
+    for (int64_t r = 0; r < K; r++) {
+      cplx s = 0;
+      for (int64_t c = 0; c < K; c++) s += (u[2 * (r * K + c)] + I * u[2 * (r * K + c) + 1]) * v[c];
+      a[idx[r]] = s;
+    }
+  }
+}
+
+/*
  * Measurement probabilities: full[i] = |a_i|^2 (if full != NULL),
  * p1[k] = sum of |a_i|^2 over indices with bit k set (the probability of
  * reading qubit k as 1), and *norm2 = sum of all |a_i|^2.

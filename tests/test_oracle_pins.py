@@ -316,3 +316,99 @@ def test_inner_product_matches_vdot():
     ref = np.vdot(a, b)
     assert abs(got.real - ref.real) <= 1e-15 and abs(got.imag - ref.imag) <= 1e-15
     assert abs(O.inner(a, 1j * a, n) - 1j) <= 1e-15
+
+
+# ------------------------------------------------------------ k-qubit gates
+
+def _haar(dim, rng):
+    z = (rng.standard_normal((dim, dim)) + 1j * rng.standard_normal((dim, dim))) / np.sqrt(2)
+    q, r = np.linalg.qr(z)
+    return q * (np.diag(r) / np.abs(np.diag(r)))
+
+
+def _dense_kq(n, targets, u):
+    """The full 2^n operator of u on `targets`, entry by entry from its
+    definition: <i|M|j> = u[r(i), r(j)] when i and j agree outside the
+    targets (r(x) = the target bits of x, bit j from qubit targets[j])."""
+    N = 1 << n
+    tmask = sum(1 << t for t in targets)
+    def r(x):
+        return sum(((x >> t) & 1) << j for j, t in enumerate(targets))
+    m = np.zeros((N, N), dtype=np.complex128)
+    for i in range(N):
+        for j in range(N):
+            if (i & ~tmask) == (j & ~tmask):
+                m[i, j] = u[r(i), r(j)]
+    return m
+
+
+@pytest.mark.parametrize("n,targets", [(4, [0]), (4, [3, 1]), (5, [1, 4, 0]), (6, [5, 2, 0, 3]),
+                                       (6, [0, 1, 2, 3, 4]), (6, [4, 0, 5, 1, 3])])
+def test_kq_matches_dense_operator(n, targets):
+    rng = np.random.default_rng(50 + n + len(targets))
+    u = _haar(1 << len(targets), rng)
+    psi = BF.random_state(n, rng)
+    ref = _dense_kq(n, targets, u) @ psi
+    out = O.apply_kq(psi.copy(), n, targets, u)
+    assert np.abs(out - ref).max() <= 1e-14
+
+
+def test_kq_index_order_matches_kronecker():
+    """u = A (x) B with B on targets[0] and A on targets[1]: numpy's kron
+    puts B on bit 0 of u's index, which is qubit targets[0]."""
+    rng = np.random.default_rng(61)
+    n = 5
+    a, b = _haar(2, rng), _haar(2, rng)
+    psi = BF.random_state(n, rng)
+    out = O.apply_kq(psi.copy(), n, [3, 1], np.kron(a, b))
+    ref = BF.kron_chain({3: b, 1: a}, n) @ psi
+    assert np.abs(out - ref).max() <= 1e-14
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
+def test_kq_of_kronecker_product_equals_single_qubit_gates(k):
+    rng = np.random.default_rng(70 + k)
+    n = 9
+    targets = [int(t) for t in rng.choice(n, k, replace=False)]
+    qs = [_haar(2, rng) for _ in range(k)]
+    u = np.ones((1, 1), dtype=np.complex128)
+    for q in reversed(qs):  # qs[j] on bit j of u's index
+        u = np.kron(u, q)
+    psi = BF.random_state(n, rng)
+    out = O.apply_kq(psi.copy(), n, targets, u)
+    ref = psi.copy()
+    for t, q in zip(targets, qs):
+        O.apply_1q(ref, n, t, q)
+    assert np.abs(out - ref).max() <= 1e-14
+
+
+@pytest.mark.parametrize("c,t", [(0, 3), (4, 1), (2, 5)])
+def test_kq_controlled_block_equals_cu(c, t):
+    rng = np.random.default_rng(80 + c)
+    n = 6
+    q = _haar(2, rng)
+    u = np.eye(4, dtype=np.complex128)
+    u[2:, 2:] = q  # index bit 1 = control (targets[1]), bit 0 = target
+    psi = BF.random_state(n, rng)
+    out = O.apply_kq(psi.copy(), n, [t, c], u)
+    ref = O.apply_cu(psi.copy(), n, c, t, q)
+    assert np.abs(out - ref).max() <= 1e-15
+
+
+def test_kq_then_inverse_returns_input():
+    rng = np.random.default_rng(90)
+    n = 10
+    for k in (2, 3, 5):
+        targets = [int(t) for t in rng.choice(n, k, replace=False)]
+        u = _haar(1 << k, rng)
+        psi = BF.random_state(n, rng)
+        out = O.apply_kq(psi.copy(), n, targets, u)
+        O.apply_kq(out, n, targets, u.conj().T)
+        assert np.abs(out - psi).max() <= 1e-13
+
+
+def test_kq_rejects_bad_targets():
+    psi = BF.random_state(4, np.random.default_rng(1))
+    for t in ([], [0, 0], [4], [-1], [0, 1, 2, 3, 0, 1]):
+        with pytest.raises(ValueError):
+            O.apply_kq(psi.copy(), 4, t, np.eye(1 << max(1, len(t))))
