@@ -22,7 +22,8 @@ Extra objects on the same JSON line: `roofline` for the dominant kernel
 (the CPU oracle on a bounded sample), `stream_copy` (measured B_mem) and
 per-category detail.  Further sections (each skippable): n=33 / n=34 large
 states, the QFT / IQFT fused-vs-unfused sweep (n = 18..31, effective
-bandwidth in the paper's sense), adjoint vs parameter-shift gradients
+bandwidth in the paper's sense), dense k-qubit gates (k = 1..5), adjoint vs
+parameter-shift gradients
 (n=20, n=28), and the batched persistent launch (4096 small ansatz
 circuits, energy + gradient).  One GPU only: --gpus above 1 exits with a
 message.
@@ -58,6 +59,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-launch section")
     ap.add_argument("--no-qft", action="store_true",
                     help="skip the QFT/IQFT fused-vs-unfused sweep (n = 18..31)")
+    ap.add_argument("--no-kq", action="store_true", help="skip the dense k-qubit gate section")
     ap.add_argument("--ps-pairs", type=int, default=8,
                     help="parameter-shift pairs timed at n=28 (extrapolated to all 2P sweeps)")
     ap.add_argument("--cpu-n", type=int, default=0, help="qubits of the CPU-oracle sample (0 = auto)")
@@ -259,6 +261,33 @@ def qft_section(Q, C, np, torch):
             torch.cuda.empty_cache()
         log(f"[bench] qft sweep {name}: n={ns[0]}..{ns[-1]} done")
         out[name] = rows
+    return out
+
+
+def kq_section(Q, C, np, torch, n):
+    """Dense gates on k = 1..5 qubits (qs_apply_kq) on the n-qubit complex128
+    state: HBM bandwidth (2 * 2^n * 16 bytes per gate) and FP64 rate (8 * 2^k
+    flop per amplitude) for the lowest, the highest and spread-out target
+    sets."""
+    out = {}
+    stream = torch.cuda.current_stream()
+    S = (1 << n) * 16
+    st = Q.State(n, Q.QS_C128, stream=stream)
+    rng = np.random.default_rng(C.SEED_BASE + 5)
+    for k in range(1, Q.QS_KQ_MAX + 1):
+        dim = 1 << k
+        z = (rng.standard_normal((dim, dim)) + 1j * rng.standard_normal((dim, dim))) / np.sqrt(2)
+        u, _ = np.linalg.qr(z)
+        rec = {}
+        for label, targets in (("low", list(range(k))), ("high", list(range(n - k, n))),
+                               ("spread", [int(round(j * (n - 1) / max(1, k - 1))) for j in range(k)])):
+            t = timed(lambda: st.apply_kq(targets, u), stream, 3)
+            rec[label] = {"targets": targets, "ms": round(t * 1e3, 3), "GBps": round(2 * S / t / 1e9, 1),
+                          "TFLOPs": round(8 * dim * (1 << n) / t / 1e12, 2)}
+        out[f"k{k}"] = rec
+    del st
+    torch.cuda.empty_cache()
+    log(f"[bench] k-qubit gates n={n}: done")
     return out
 
 
@@ -562,6 +591,8 @@ def main():
         line["large_states"] = large_section(Q, C, np, torch)
     if not args.no_qft:
         line["qft_fused_vs_unfused"] = qft_section(Q, C, np, torch)
+    if not args.no_kq:
+        line["kq_gates"] = kq_section(Q, C, np, torch, n)
     if not args.no_adjoint:
         line["adjoint_vs_param_shift"] = adjoint_section(Q, C, np, torch, args.ps_pairs)
     if not args.no_batch:

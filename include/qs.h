@@ -132,6 +132,25 @@ int qs_apply_1q(qs_state* s, int k, const double* q);
 int qs_apply_cu(qs_state* s, int c, int t, const double* q);
 
 /*
+ * Dense gate on a block of k qubits, in place: Eq. (2) read for k qubits
+ * (the paper fuses gates on a set of qubits into one pass, Sec. 4.4; this
+ * takes the block's product as one matrix).  Every group of 2^k amplitudes
+ * whose indices differ only in the target bits, listed in the order of that
+ * k-bit index, is replaced by u times the group.
+ *   k        1 .. QS_KQ_MAX
+ *   targets  host, k distinct qubits in [0, n); bit j of u's row and column
+ *            index is qubit targets[j]
+ *   u        host, 2^k x 2^k complex entries, row-major, each (re, im):
+ *            2 * 4^k doubles (a complex64 state uses them rounded to float)
+ * Asynchronous on the state's stream; the matrix is copied before return.
+ * u is not checked for unitarity.
+ * Errors: QS_EINVAL (k out of range, a target out of range or repeated,
+ * NULL), QS_ENOMEM, QS_EHIP.
+ */
+#define QS_KQ_MAX 5
+int qs_apply_kq(qs_state* s, int k, const int32_t* targets, const double* u);
+
+/*
  * Apply a gate list in order, in place.  Consecutive gates may be fused
  * into one pass over the state that keeps a block of amplitudes on chip
  * while several gates are applied to it (cache blocking by gate fusion,

@@ -281,6 +281,20 @@ int qs_apply_cu(qs_state* s, int c, int t, const double* q) {
   return done(qs::launch_apply_cu(&s->impl, c, t, q));
 }
 
+int qs_apply_kq(qs_state* s, int k, const int32_t* targets, const double* u) {
+  if (!valid_state(s)) return fail(QS_EINVAL, "qs_apply_kq: bad state");
+  if (!targets || !u) return fail(QS_EINVAL, "qs_apply_kq: targets or u is NULL");
+  const int n = s->impl.n;
+  if (k < 1 || k > QS_KQ_MAX || k > n) return fail(QS_EINVAL, "qs_apply_kq: k out of range");
+  uint64_t seen = 0;
+  for (int j = 0; j < k; ++j) {
+    if (targets[j] < 0 || targets[j] >= n) return fail(QS_EINVAL, "qs_apply_kq: target out of range");
+    if ((seen >> targets[j]) & 1) return fail(QS_EINVAL, "qs_apply_kq: repeated target");
+    seen |= 1ull << targets[j];
+  }
+  return done(qs::launch_apply_kq(&s->impl, k, targets, u));
+}
+
 int qs_run(qs_state* s, const qs_op* ops, int nops, const double* theta, int nparams, int flags) {
   if (!valid_state(s)) return fail(QS_EINVAL, "qs_run: bad state");
   if (nops < 0 || (nops > 0 && !ops)) return fail(QS_EINVAL, "qs_run: bad op list");

@@ -66,6 +66,8 @@ Status launch_init_basis(StateImpl* s, uint64_t index);
 Status launch_apply_1q(StateImpl* s, int k, const double* q);
 Status launch_apply_cu(StateImpl* s, int c, int t, const double* q);
 Status launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t stream);
+// Dense 2^k x 2^k gate (u: 2 * 4^k doubles, row-major (re, im)) on targets.
+Status launch_apply_kq(StateImpl* s, int k, const int32_t* targets, const double* u);
 
 // ------------------------------------------------------------ reductions
 // Per-qubit P(bit = 1), total norm^2 and optionally the full |a_i|^2 vector.

@@ -27,6 +27,7 @@ QS_OP_U, QS_OP_CU, QS_OP_RX, QS_OP_RY, QS_OP_RZ = 0, 1, 2, 3, 4
 QS_RUN_NO_FUSION = 1
 QS_ADJ_STATE_IS_FINAL = 1
 QS_BATCH_MAX_QUBITS = 24
+QS_KQ_MAX = 5
 
 # Mirror of `struct qs_op` (80 bytes).
 QS_OP_DTYPE = np.dtype([("kind", "<i4"), ("target", "<i4"), ("control", "<i4"),
@@ -36,7 +37,7 @@ EXPORTED = ("qs_version", "qs_strerror", "qs_last_error", "qs_create", "qs_destr
             "qs_set_stream", "qs_init_basis", "qs_apply_1q", "qs_apply_cu", "qs_run",
             "qs_probabilities", "qs_expect_pauli", "qs_apply_pauli_sum", "qs_grad_adjoint",
             "qs_stream_copy", "qs_plan", "qs_batch_create", "qs_batch_run",
-            "qs_batch_destroy")
+            "qs_batch_destroy", "qs_apply_kq")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1601_07195_amd.build`")
@@ -54,6 +55,7 @@ _L.qs_set_stream.argtypes = [_vp, _vp]
 _L.qs_init_basis.argtypes = [_vp, _u64]
 _L.qs_apply_1q.argtypes = [_vp, _i, _dp]
 _L.qs_apply_cu.argtypes = [_vp, _i, _i, _dp]
+_L.qs_apply_kq.argtypes = [_vp, _i, _vp, _dp]
 _L.qs_run.argtypes = [_vp, _vp, _i, _dp, _i, _i]
 _L.qs_probabilities.argtypes = [_vp, _dp, _dp, _vp, _sz]
 _L.qs_expect_pauli.argtypes = [_vp, _i, _vp, _vp, _dp, _dp]
@@ -190,6 +192,18 @@ def qs_apply_1q(h: int, k: int, q) -> None:
 def qs_apply_cu(h: int, c: int, t: int, q) -> None:
     m = _mat8(q)
     _check(_L.qs_apply_cu(h, c, t, _ptr(m)), "qs_apply_cu")
+
+
+def qs_apply_kq(h: int, targets, u) -> None:
+    """Dense 2^k x 2^k gate u on `targets` (bit j of u's index is qubit
+    targets[j])."""
+    t = np.ascontiguousarray(targets, dtype=np.int32)
+    m = np.ascontiguousarray(np.asarray(u, dtype=np.complex128))
+    k = len(t)
+    if m.shape != (1 << k, 1 << k):
+        raise ValueError("u must be 2^k x 2^k for k targets")
+    flat = m.view(np.float64).copy()
+    _check(_L.qs_apply_kq(h, k, _ptr(t), _ptr(flat)), "qs_apply_kq")
 
 
 def qs_run(h: int, ops, theta=None, flags: int = 0) -> None:
@@ -350,6 +364,10 @@ class State:
 
     def apply_cu(self, c: int, t: int, q) -> "State":
         qs_apply_cu(self.handle, c, t, q)
+        return self
+
+    def apply_kq(self, targets, u) -> "State":
+        qs_apply_kq(self.handle, targets, u)
         return self
 
     def run(self, ops, theta=None, fuse: bool = True) -> "State":
