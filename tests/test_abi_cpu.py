@@ -88,6 +88,8 @@ def test_null_handles_rejected(Q):
     m = np.stack([q.real, q.imag], -1).reshape(8).copy()
     assert L.qs_apply_1q(None, 0, m.ctypes.data) == Q.QS_EINVAL
     assert L.qs_apply_cu(None, 0, 1, m.ctypes.data) == Q.QS_EINVAL
+    t = np.zeros(1, dtype=np.int32)
+    assert L.qs_apply_kq(None, 1, t.ctypes.data, m.ctypes.data) == Q.QS_EINVAL
     assert L.qs_init_basis(None, 0) == Q.QS_EINVAL
     assert L.qs_run(None, None, 0, None, 0, 0) == Q.QS_EINVAL
     assert L.qs_probabilities(None, None, None, None, 0) == Q.QS_EINVAL
