@@ -285,3 +285,25 @@ def test_apply_kq_rejects_bad_arguments(Q):
     m = np.zeros(8)
     assert L.qs_apply_kq(st.handle, 0, t.ctypes.data, m.ctypes.data) == Q.QS_EINVAL
     assert L.qs_apply_kq(None, 1, t.ctypes.data, m.ctypes.data) == Q.QS_EINVAL
+
+
+@pytest.mark.parametrize("name", ["c128", "c64"])
+def test_phase_gates_touch_only_their_quarter(Q, name):
+    """diag(1, phi) single-qubit and controlled gates (the quarter-state
+    phase kernel) against the oracle, for low, middle and top qubits."""
+    dtype = Q.QS_C128 if name == "c128" else Q.QS_C64
+    n = 14
+    rng = np.random.default_rng(1300)
+    psi = random_state(n, rng)
+    st = to_gpu_state(Q, psi, dtype)
+    ref = st.numpy().astype(np.complex128)
+    tol = 1e-13 if name == "c128" else 3e-6
+    for k in (0, 1, 2, 3, 7, n - 1):
+        ph = np.diag([1.0, np.exp(1j * rng.uniform(0, 2 * np.pi))])
+        st.apply_1q(k, ph)
+        O.apply_1q(ref, n, k, ph)
+    for c, t in ((0, 1), (1, 0), (2, 9), (9, 2), (0, n - 1), (n - 1, 5), (4, 3)):
+        ph = np.diag([1.0, np.exp(1j * rng.uniform(0, 2 * np.pi))])
+        st.apply_cu(c, t, ph)
+        O.apply_cu(ref, n, c, t, ph)
+    assert np.abs(st.numpy() - ref).max() <= tol
