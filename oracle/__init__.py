@@ -44,6 +44,8 @@ def lib():
         L.oracle_apply_1q.argtypes = [vp, i, i, vp]
         L.oracle_apply_cu.argtypes = [vp, i, i, i, vp]
         L.oracle_apply_kq.argtypes = [vp, i, i, vp, vp]
+        L.oracle_permute_qubits.argtypes = [vp, i, vp]
+        L.oracle_permute_qubits.restype = i
         L.oracle_probabilities.argtypes = [vp, i, vp, vp, vp]
         L.oracle_inner.argtypes = [vp, vp, i, _dp, _dp]
         L.oracle_apply_pauli_string.argtypes = [vp, i, vp, vp]
@@ -123,6 +125,18 @@ def apply_kq(psi: np.ndarray, n: int, targets, u) -> np.ndarray:
         raise ValueError("u must be 2^k x 2^k")
     flat = np.ascontiguousarray(m).view(np.float64).copy()
     lib().oracle_apply_kq(_ptr(_state(psi, n)), n, k, _ptr(t), _ptr(flat))
+    return psi
+
+
+def permute_qubits(psi: np.ndarray, n: int, perm) -> np.ndarray:
+    """In place: relabel qubit q as qubit perm[q] (state reordering, Sec. 6):
+    the amplitude of index i moves to the index whose bit perm[q] is bit q
+    of i."""
+    p = np.ascontiguousarray(perm, dtype=np.int32)
+    if p.shape != (n,) or sorted(p.tolist()) != list(range(n)):
+        raise ValueError("perm must be a permutation of 0..n-1")
+    if lib().oracle_permute_qubits(_ptr(_state(psi, n)), n, _ptr(p)) != 0:
+        raise MemoryError("oracle_permute_qubits: no memory for the copy")
     return psi
 
 

@@ -148,6 +148,29 @@ void oracle_apply_kq(cplx* a, int n, int k, const int* targets, const double* u)
 }
 
 /*
+ * Qubit reordering (the state reordering of Sec. 6): qubit q is relabelled
+ * perm[q], so the amplitude at index i moves to the index j that has bit
+ * perm[q] equal to bit q of i, for every q.  perm must be a permutation of
+ * 0 .. n-1.  Out of place through a temporary copy of the state.
+ * Returns 0, or -1 if the copy cannot be allocated.
+ */
+int oracle_permute_qubits(cplx* a, int n, const int* perm) {
+  const int64_t N = (int64_t)1 << n;
+  cplx* src = (cplx*)malloc((size_t)N * sizeof(cplx));
+  if (!src) return -1;
+  memcpy(src, a, (size_t)N * sizeof(cplx));
+#pragma omp parallel for num_threads(g_threads) if (g_threads > 1) schedule(static)
+  for (int64_t i = 0; i < N; i++) {
+    int64_t j = 0;
+    for (int q = 0; q < n; q++)
+      if ((i >> q) & 1) j |= (int64_t)1 << perm[q];
+    a[j] = src[i];
+  }
+  free(src);
+  return 0;
+}
+
+/*
  * Measurement probabilities: full[i] = |a_i|^2 (if full != NULL),
  * p1[k] = sum of |a_i|^2 over indices with bit k set (the probability of
  * reading qubit k as 1), and *norm2 = sum of all |a_i|^2.

@@ -412,3 +412,82 @@ def test_kq_rejects_bad_targets():
     for t in ([], [0, 0], [4], [-1], [0, 1, 2, 3, 0, 1]):
         with pytest.raises(ValueError):
             O.apply_kq(psi.copy(), 4, t, np.eye(1 << max(1, len(t))))
+
+
+# ------------------------------------------- qubit reordering (Sec. 6)
+
+def _product_state(vecs, n):
+    """|phi_{n-1}> (x) ... (x) |phi_0>, qubit q's factor vecs[q] (qubit q is
+    bit q of the index, so it is the last Kronecker factor for q = 0)."""
+    out = np.ones(1, dtype=np.complex128)
+    for q in reversed(range(n)):
+        out = np.kron(out, vecs[q])
+    return out
+
+
+def _random_qubit_states(n, r):
+    v = r.standard_normal((n, 2)) + 1j * r.standard_normal((n, 2))
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 8])
+def test_permute_moves_product_state_factors(n):
+    """Relabelling qubit q as perm[q] puts qubit q's factor of a product state
+    at position perm[q]."""
+    r = rng(200 + n)
+    for _ in range(4):
+        vecs = _random_qubit_states(n, r)
+        perm = [int(x) for x in r.permutation(n)]
+        got = O.permute_qubits(_product_state(vecs, n), n, perm)
+        moved = [None] * n
+        for q in range(n):
+            moved[perm[q]] = vecs[q]
+        assert np.abs(got - _product_state(moved, n)).max() <= 1e-15
+
+
+@pytest.mark.parametrize("n", [3, 6, 9])
+def test_permute_is_a_tensor_axis_transpose(n):
+    """On the state as an n-axis tensor (axis a = qubit n-1-a) the relabelling
+    is numpy's axis transpose."""
+    r = rng(210 + n)
+    psi = BF.random_state(n, r)
+    perm = [int(x) for x in r.permutation(n)]
+    inv = [0] * n
+    for q in range(n):
+        inv[perm[q]] = q
+    axes = [n - 1 - inv[n - 1 - b] for b in range(n)]
+    ref = np.transpose(psi.reshape((2,) * n), axes).reshape(-1)
+    assert np.array_equal(O.permute_qubits(psi.copy(), n, perm), ref)
+
+
+@pytest.mark.parametrize("a,b", [(0, 1), (1, 0), (2, 6), (6, 0)])
+def test_permute_swap_equals_three_cnots(a, b):
+    n = 7
+    psi = BF.random_state(n, rng(220 + a * 7 + b))
+    perm = list(range(n))
+    perm[a], perm[b] = b, a
+    ref = O.apply_cu(psi.copy(), n, a, b, C.X_GATE)
+    O.apply_cu(ref, n, b, a, C.X_GATE)
+    O.apply_cu(ref, n, a, b, C.X_GATE)
+    assert np.array_equal(O.permute_qubits(psi.copy(), n, perm), ref)
+
+
+def test_permute_composes_and_inverts():
+    n = 9
+    r = rng(230)
+    psi = BF.random_state(n, r)
+    p1 = [int(x) for x in r.permutation(n)]
+    p2 = [int(x) for x in r.permutation(n)]
+    two = O.permute_qubits(O.permute_qubits(psi.copy(), n, p1), n, p2)
+    assert np.array_equal(two, O.permute_qubits(psi.copy(), n, [p2[p1[q]] for q in range(n)]))
+    inv = [0] * n
+    for q in range(n):
+        inv[p1[q]] = q
+    assert np.array_equal(O.permute_qubits(O.permute_qubits(psi.copy(), n, p1), n, inv), psi)
+
+
+def test_permute_rejects_non_permutations():
+    psi = BF.random_state(4, rng(240))
+    for p in ([0, 1, 2], [0, 1, 2, 2], [0, 1, 2, 4], [-1, 0, 1, 2]):
+        with pytest.raises(ValueError):
+            O.permute_qubits(psi.copy(), 4, p)
