@@ -60,6 +60,7 @@ def parse():
     ap.add_argument("--no-qft", action="store_true",
                     help="skip the QFT/IQFT fused-vs-unfused sweep (n = 18..31)")
     ap.add_argument("--no-kq", action="store_true", help="skip the dense k-qubit gate section")
+    ap.add_argument("--no-reorder", action="store_true", help="skip the qubit-reordering section")
     ap.add_argument("--ps-pairs", type=int, default=8,
                     help="parameter-shift pairs timed at n=28 (extrapolated to all 2P sweeps)")
     ap.add_argument("--cpu-n", type=int, default=0, help="qubits of the CPU-oracle sample (0 = auto)")
@@ -288,6 +289,53 @@ def kq_section(Q, C, np, torch, n):
     del st
     torch.cuda.empty_cache()
     log(f"[bench] k-qubit gates n={n}: done")
+    return out
+
+
+def reorder_section(Q, C, np, torch, n):
+    """Qubit reordering (Sec. 6) on the n-qubit complex128 state.  The
+    permutation kernels: swaps of upper qubits move only the 1 KiB blocks
+    that change place, 2 (1 - 2^-k) S bytes for k swaps; a swap that touches
+    a block bit moves 2 S.  Then the reordered runner for a state split by
+    its top 3 qubits (8 shards), against the plain run of the same circuits:
+    the reorderings it inserts and the network traffic per shard with them
+    and with Sec. 3.2's pairwise exchanges (Table 2's counts)."""
+    out = {"permute": {}, "runs": {}}
+    stream = torch.cuda.current_stream()
+    S = (1 << n) * 16
+    st = Q.State(n, Q.QS_C128, stream=stream)
+
+    def swaps(pairs):
+        p = list(range(n))
+        for a, b in pairs:
+            p[a], p[b] = b, a
+        return p
+
+    cases = (("one_upper_swap", swaps([(n - 1, 9)]), 2 * 0.5 * S),
+             ("three_upper_swaps", swaps([(n - 1, 9), (n - 2, 8), (n - 3, 7)]), 2 * 0.875 * S),
+             ("block_bit_swap", swaps([(0, n - 1)]), 2 * S),
+             ("reverse", list(range(n))[::-1], None))
+    for label, perm, nbytes in cases:
+        t = timed(lambda: st.permute_qubits(perm), stream, 4)
+        rec = {"ms": round(t * 1e3, 3)}
+        if nbytes:
+            rec["bytes"] = nbytes
+            rec["GBps"] = round(nbytes / t / 1e9, 1)
+        out["permute"][label] = rec
+    for label, ops in (("random1000", C.random_circuit(n, 1000, np.random.default_rng(C.SEED_BASE + 1)).ops),
+                       ("random500_qft", C.workload_circuit_qft(n, 500).ops)):
+        t_plain = timed(lambda: st.run(ops), stream, 1)
+        info = {}
+
+        def reordered():
+            info.update(st.run_reordered(ops, n - 3))
+
+        t_re = timed(reordered, stream, 1)
+        out["runs"][label] = {"plain_ms": round(t_plain * 1e3, 1), "reordered_ms": round(t_re * 1e3, 1),
+                              "upper_qubits": 3, **info}
+    del st
+    torch.cuda.empty_cache()
+    log(f"[bench] qubit reordering n={n}: done")
     return out
 
 
@@ -593,6 +641,8 @@ def main():
         line["qft_fused_vs_unfused"] = qft_section(Q, C, np, torch)
     if not args.no_kq:
         line["kq_gates"] = kq_section(Q, C, np, torch, n)
+    if not args.no_reorder:
+        line["qubit_reordering"] = reorder_section(Q, C, np, torch, n)
     if not args.no_adjoint:
         line["adjoint_vs_param_shift"] = adjoint_section(Q, C, np, torch, args.ps_pairs)
     if not args.no_batch:

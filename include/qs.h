@@ -167,6 +167,81 @@ int qs_run(qs_state* s, const qs_op* ops, int nops, const double* theta,
            int nparams, int flags);
 
 /*
+ * Qubit reordering in place (the state reordering of Sec. 6): qubit q is
+ * relabelled perm[q], so the amplitude at index i moves to the index whose
+ * bit perm[q] equals bit q of i, for every q.  A swap of two qubits is the
+ * permutation that exchanges them.
+ *   perm  host, n int32: a permutation of 0 .. n-1 (copied before return)
+ * Runs as at most two passes of disjoint qubit swaps, each one or two
+ * launches: swaps of two qubits above the 1 KiB block bits (6 for complex128,
+ * 7 for complex64) move only the blocks that change place, 2 (1 - 2^-k) S
+ * bytes for k swaps (S = the state's bytes); swaps that touch a block bit
+ * move 2 S bytes per launch of up to four.  The identity launches nothing.
+ * Asynchronous on the state's stream; no scratch memory.
+ * Errors: QS_EINVAL (NULL, not a permutation), QS_EHIP.
+ */
+int qs_permute_qubits(qs_state* s, const int32_t* perm);
+
+/*
+ * Counts of a qubit-reordering plan for a state split over 2^(n - nlocal)
+ * shards by its top n - nlocal qubits (Sec. 3.2's distribution, with the
+ * reordering of Sec. 6).  Traffic is the bytes each shard sends plus
+ * receives, in units of its own share of the state.
+ */
+typedef struct qs_reorder_info {
+  int32_t remaps;            /* reorderings inserted before gates */
+  int32_t swaps;             /* upper/local qubit swaps they make in total */
+  int32_t restore_swaps;     /* upper positions the final reordering (back to
+                                the caller's order) refills; 0 = none needed */
+  int32_t global_gates;      /* non-diagonal gates whose target is an upper
+                                qubit in the caller's order: one pairwise
+                                exchange each in Sec. 3.2's scheme */
+  double traffic_reordered;  /* all reorderings, the final one included: a
+                                reordering of k swaps keeps 2^-k of each
+                                shard's amplitudes, 2 (1 - 2^-k) */
+  double traffic_pairwise;   /* the pairwise exchanges as Table 2 counts them:
+                                2 per global gate (cases 2 and 6), 1 if its
+                                control is local (case 5) */
+} qs_reorder_info;
+
+/*
+ * Plan the reordering of a gate list (host only, no GPU needed).  A
+ * non-diagonal gate whose target sits at an upper position triggers one
+ * reordering that swaps it in, with every other upper qubit needed before
+ * the local qubit it would displace; diagonal gates and controls never need
+ * one.  Running, for r = 0, 1, ..., the gates out_ops[remap_at[r-1] ..
+ * remap_at[r]) (from 0 for r = 0) followed by qs_permute_qubits(remap_perm +
+ * r * n), then the remaining gates and qs_permute_qubits(final_perm), equals
+ * qs_run of the original list.
+ *   nlocal      1 .. n: qubits below it are local to a shard
+ *   theta       as for qs_run (needed only to validate rotations)
+ *   info        host, may be NULL
+ *   out_ops     host, nops records or NULL: the gates with target and control
+ *               replaced by their positions at that point; if NULL only info
+ *               is filled and the arrays below are not touched
+ *   remap_at    host, cap int32: the gate each reordering precedes
+ *   remap_perm  host, cap * n int32: the reorderings
+ *   cap         capacity of remap_at / remap_perm in reorderings
+ *   final_perm  host, n int32: the reordering back to the caller's order
+ * Errors: QS_EINVAL (bad arguments or op list), QS_ERANGE (cap smaller than
+ * info->remaps; info is still filled).
+ */
+int qs_plan_reorder(int n, int nlocal, const qs_op* ops, int nops, const double* theta,
+                    int nparams, qs_reorder_info* info, qs_op* out_ops, int32_t* remap_at,
+                    int32_t* remap_perm, int cap, int32_t* final_perm);
+
+/*
+ * qs_run through a reordering plan: the gates between reorderings run as
+ * qs_run runs them (flags as there), the reorderings as qs_permute_qubits,
+ * and the state ends in the caller's qubit order, equal to qs_run's result
+ * up to floating-point rounding.  This is how one shard's share of a split
+ * state would be processed on one GPU; info (host, may be NULL) receives
+ * the plan's counts.
+ */
+int qs_run_reordered(qs_state* s, int nlocal, const qs_op* ops, int nops, const double* theta,
+                     int nparams, int flags, qs_reorder_info* info);
+
+/*
  * Measurement probabilities of the state (not part of the paper; the
  * per-qubit marginals of |alpha_i|^2):
  *   p1     host, n doubles or NULL: p1[k] = sum over i with bit k set of |alpha_i|^2

@@ -23,7 +23,7 @@ OBJDIR = os.path.join(HERE, "_build")
 ARCH = "gfx950"
 
 SOURCES = ["qs_api.cpp", "qs_plan.cpp", "qs_gates.hip", "qs_reduce.hip", "qs_fused.hip",
-           "qs_adjoint.hip", "qs_batch.hip", "qs_kq.hip"]
+           "qs_adjoint.hip", "qs_batch.hip", "qs_kq.hip", "qs_perm.hip", "qs_reorder.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{INCLUDE}", f"-I{CSRC}", "-Wall"]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

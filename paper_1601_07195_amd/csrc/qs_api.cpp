@@ -295,6 +295,19 @@ int qs_apply_kq(qs_state* s, int k, const int32_t* targets, const double* u) {
   return done(qs::launch_apply_kq(&s->impl, k, targets, u));
 }
 
+int qs_permute_qubits(qs_state* s, const int32_t* perm) {
+  if (!valid_state(s)) return fail(QS_EINVAL, "qs_permute_qubits: bad state");
+  if (!perm) return fail(QS_EINVAL, "qs_permute_qubits: perm is NULL");
+  const int n = s->impl.n;
+  uint64_t seen = 0;
+  for (int q = 0; q < n; ++q) {
+    if (perm[q] < 0 || perm[q] >= n) return fail(QS_EINVAL, "qs_permute_qubits: entry out of range");
+    if ((seen >> perm[q]) & 1) return fail(QS_EINVAL, "qs_permute_qubits: not a permutation");
+    seen |= 1ull << perm[q];
+  }
+  return done(qs::launch_permute(&s->impl, perm));
+}
+
 int qs_run(qs_state* s, const qs_op* ops, int nops, const double* theta, int nparams, int flags) {
   if (!valid_state(s)) return fail(QS_EINVAL, "qs_run: bad state");
   if (nops < 0 || (nops > 0 && !ops)) return fail(QS_EINVAL, "qs_run: bad op list");
@@ -407,6 +420,49 @@ int qs_plan(int n, int dtype, const qs_op* ops, int nops, const double* theta, i
     if (pass_of) pass_of[g] = plan.pass_of[g];
   }
   return QS_OK;
+}
+
+int qs_plan_reorder(int n, int nlocal, const qs_op* ops, int nops, const double* theta,
+                    int nparams, qs_reorder_info* info, qs_op* out_ops, int32_t* remap_at,
+                    int32_t* remap_perm, int cap, int32_t* final_perm) {
+  if (n < 1 || n > QS_MAX_QUBITS_C64) return fail(QS_ERANGE, "qs_plan_reorder: n out of range");
+  if (nlocal < 1 || nlocal > n) return fail(QS_EINVAL, "qs_plan_reorder: nlocal out of range");
+  if (nops < 0 || (nops > 0 && !ops)) return fail(QS_EINVAL, "qs_plan_reorder: bad op list");
+  if (nparams < 0) return fail(QS_EINVAL, "qs_plan_reorder: nparams < 0");
+  if (out_ops && (cap < 0 || !final_perm || (cap > 0 && (!remap_at || !remap_perm))))
+    return fail(QS_EINVAL, "qs_plan_reorder: NULL output array");
+  std::vector<qs::XGate> gates;
+  Status st = qs::normalize_ops(n, ops, nops, theta, nparams, &gates);
+  if (!st.good()) return done(st);
+  qs::ReorderPlan plan;
+  st = qs::plan_reorder(n, nlocal, gates, &plan);
+  if (!st.good()) return done(st);
+  if (info) *info = plan.info;
+  if (!out_ops) return QS_OK;
+  const int R = (int)plan.remap_at.size();
+  if (R > cap) return fail(QS_ERANGE, "qs_plan_reorder: cap smaller than the number of reorderings");
+  for (int g = 0; g < nops; ++g) {
+    out_ops[g] = ops[g];
+    out_ops[g].target = plan.tgt[g];
+    if (ops[g].kind == QS_OP_CU) out_ops[g].control = plan.ctl[g];
+  }
+  for (int r = 0; r < R; ++r) remap_at[r] = plan.remap_at[r];
+  if (R > 0) memcpy(remap_perm, plan.remap_perm.data(), (size_t)R * n * sizeof(int32_t));
+  memcpy(final_perm, plan.final_perm.data(), (size_t)n * sizeof(int32_t));
+  return QS_OK;
+}
+
+int qs_run_reordered(qs_state* s, int nlocal, const qs_op* ops, int nops, const double* theta,
+                     int nparams, int flags, qs_reorder_info* info) {
+  if (!valid_state(s)) return fail(QS_EINVAL, "qs_run_reordered: bad state");
+  if (nlocal < 1 || nlocal > s->impl.n) return fail(QS_EINVAL, "qs_run_reordered: nlocal out of range");
+  if (nops < 0 || (nops > 0 && !ops)) return fail(QS_EINVAL, "qs_run_reordered: bad op list");
+  if (nparams < 0) return fail(QS_EINVAL, "qs_run_reordered: nparams < 0");
+  if (flags & ~QS_RUN_NO_FUSION) return fail(QS_EINVAL, "qs_run_reordered: unknown flags");
+  std::vector<qs::XGate> gates;
+  Status st = qs::normalize_ops(s->impl.n, ops, nops, theta, nparams, &gates);
+  if (!st.good()) return done(st);
+  return done(qs::run_reordered(&s->impl, nlocal, gates, flags, info));
 }
 
 int qs_batch_create(int dtype, int ncircuits, const int32_t* n, const int64_t* op_off,

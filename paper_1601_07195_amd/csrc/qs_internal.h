@@ -68,6 +68,8 @@ Status launch_apply_cu(StateImpl* s, int c, int t, const double* q);
 Status launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t stream);
 // Dense 2^k x 2^k gate (u: 2 * 4^k doubles, row-major (re, im)) on targets.
 Status launch_apply_kq(StateImpl* s, int k, const int32_t* targets, const double* u);
+// Relabel qubit q as perm[q] in place (perm: host, a permutation of 0..n-1).
+Status launch_permute(StateImpl* s, const int32_t* perm);
 
 // ------------------------------------------------------------ reductions
 // Per-qubit P(bit = 1), total norm^2 and optionally the full |a_i|^2 vector.
@@ -110,6 +112,18 @@ struct XGate {
 Status normalize_ops(int n, const qs_op* ops, int nops, const double* theta, int nparams,
                      std::vector<XGate>* out);
 Status run_gates(StateImpl* s, const std::vector<XGate>& gates, int flags);
+
+// Qubit-reordering plan for a state split by its top n - nlocal qubits.
+struct ReorderPlan {
+  std::vector<int> tgt, ctl;         // each gate's target / control position (-1: none)
+  std::vector<int> remap_at;         // reordering r comes just before gate remap_at[r]
+  std::vector<int32_t> remap_perm;   // its permutation of positions, n entries each
+  std::vector<int32_t> final_perm;   // back to the caller's qubit order
+  qs_reorder_info info;
+};
+Status plan_reorder(int n, int nlocal, const std::vector<XGate>& gates, ReorderPlan* out);
+Status run_reordered(StateImpl* s, int nlocal, const std::vector<XGate>& gates, int flags,
+                     qs_reorder_info* info);
 
 // ------------------------------------------------------- fusion planning
 // A fused pass keeps one tile of 2^T amplitudes on chip per workgroup: the

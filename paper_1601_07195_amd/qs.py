@@ -37,7 +37,8 @@ EXPORTED = ("qs_version", "qs_strerror", "qs_last_error", "qs_create", "qs_destr
             "qs_set_stream", "qs_init_basis", "qs_apply_1q", "qs_apply_cu", "qs_run",
             "qs_probabilities", "qs_expect_pauli", "qs_apply_pauli_sum", "qs_grad_adjoint",
             "qs_stream_copy", "qs_plan", "qs_batch_create", "qs_batch_run",
-            "qs_batch_destroy", "qs_apply_kq")
+            "qs_batch_destroy", "qs_apply_kq", "qs_permute_qubits", "qs_plan_reorder",
+            "qs_run_reordered")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1601_07195_amd.build`")
@@ -72,6 +73,18 @@ class QSPlanInfo(ctypes.Structure):
 
 
 _L.qs_plan.argtypes = [_i, _i, _vp, _i, _dp, _i, _i, ctypes.POINTER(QSPlanInfo), _vp, _vp]
+
+
+class QSReorderInfo(ctypes.Structure):
+    _fields_ = [("remaps", ctypes.c_int32), ("swaps", ctypes.c_int32),
+                ("restore_swaps", ctypes.c_int32), ("global_gates", ctypes.c_int32),
+                ("traffic_reordered", ctypes.c_double), ("traffic_pairwise", ctypes.c_double)]
+
+
+_L.qs_permute_qubits.argtypes = [_vp, _vp]
+_L.qs_plan_reorder.argtypes = [_i, _i, _vp, _i, _dp, _i, ctypes.POINTER(QSReorderInfo), _vp, _vp,
+                               _vp, _i, _vp]
+_L.qs_run_reordered.argtypes = [_vp, _i, _vp, _i, _dp, _i, _i, ctypes.POINTER(QSReorderInfo)]
 
 
 class QSBatchTuning(ctypes.Structure):
@@ -266,6 +279,45 @@ def qs_plan(n: int, dtype: int, ops, theta=None, flags: int = 0):
     return d, order, pass_of
 
 
+def qs_permute_qubits(h: int, perm) -> None:
+    """Relabel qubit q as perm[q] in place (state reordering, Sec. 6)."""
+    p = np.ascontiguousarray(perm, dtype=np.int32)
+    _check(_L.qs_permute_qubits(h, _ptr(p)), "qs_permute_qubits")
+
+
+def _reorder_dict(info):
+    return {f: getattr(info, f) for f, _ in QSReorderInfo._fields_}
+
+
+def qs_plan_reorder(n: int, nlocal: int, ops, theta=None):
+    """Host-only reordering plan for a state split by its top n - nlocal
+    qubits: returns (info dict, ops on positions, remap_at, remap_perm
+    [R x n], final_perm)."""
+    a = ops_array(ops)
+    th = _f64(theta) if theta is not None else None
+    nth = 0 if th is None else len(th)
+    info = QSReorderInfo()
+    _check(_L.qs_plan_reorder(n, nlocal, _ptr(a), len(a), _ptr(th), nth, ctypes.byref(info),
+                              None, None, None, 0, None), "qs_plan_reorder")
+    R = info.remaps
+    out = np.zeros(len(a), dtype=QS_OP_DTYPE)
+    at = np.zeros(max(R, 1), dtype=np.int32)
+    perm = np.zeros((max(R, 1), n), dtype=np.int32)
+    fin = np.zeros(n, dtype=np.int32)
+    _check(_L.qs_plan_reorder(n, nlocal, _ptr(a), len(a), _ptr(th), nth, ctypes.byref(info),
+                              _ptr(out), _ptr(at), _ptr(perm), R, _ptr(fin)), "qs_plan_reorder")
+    return _reorder_dict(info), out, at[:R].copy(), perm[:R].copy(), fin
+
+
+def qs_run_reordered(h: int, nlocal: int, ops, theta=None, flags: int = 0):
+    a = ops_array(ops)
+    th = _f64(theta) if theta is not None else None
+    info = QSReorderInfo()
+    _check(_L.qs_run_reordered(h, nlocal, _ptr(a), len(a), _ptr(th), 0 if th is None else len(th),
+                               flags, ctypes.byref(info)), "qs_run_reordered")
+    return _reorder_dict(info)
+
+
 def qs_stream_copy(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
     nbytes = src.numel() * src.element_size()
     if dst.numel() * dst.element_size() < nbytes:
@@ -373,6 +425,13 @@ class State:
     def run(self, ops, theta=None, fuse: bool = True) -> "State":
         qs_run(self.handle, ops, theta, 0 if fuse else QS_RUN_NO_FUSION)
         return self
+
+    def permute_qubits(self, perm) -> "State":
+        qs_permute_qubits(self.handle, perm)
+        return self
+
+    def run_reordered(self, ops, nlocal: int, theta=None, fuse: bool = True) -> dict:
+        return qs_run_reordered(self.handle, nlocal, ops, theta, 0 if fuse else QS_RUN_NO_FUSION)
 
     def probabilities(self, full: bool = False):
         ft = torch.empty(1 << self.n, dtype=torch.float64, device=self.tensor.device) if full else None

@@ -31,7 +31,8 @@ def declared_functions():
 def test_header_declares_expected_api():
     names = declared_functions()
     for must in ("qs_create", "qs_apply_1q", "qs_apply_cu", "qs_probabilities",
-                 "qs_expect_pauli", "qs_grad_adjoint"):
+                 "qs_expect_pauli", "qs_grad_adjoint", "qs_permute_qubits",
+                 "qs_plan_reorder", "qs_run_reordered"):
         assert must in names
 
 
@@ -90,6 +91,8 @@ def test_null_handles_rejected(Q):
     assert L.qs_apply_cu(None, 0, 1, m.ctypes.data) == Q.QS_EINVAL
     t = np.zeros(1, dtype=np.int32)
     assert L.qs_apply_kq(None, 1, t.ctypes.data, m.ctypes.data) == Q.QS_EINVAL
+    assert L.qs_permute_qubits(None, t.ctypes.data) == Q.QS_EINVAL
+    assert L.qs_run_reordered(None, 1, None, 0, None, 0, 0, None) == Q.QS_EINVAL
     assert L.qs_init_basis(None, 0) == Q.QS_EINVAL
     assert L.qs_run(None, None, 0, None, 0, 0) == Q.QS_EINVAL
     assert L.qs_probabilities(None, None, None, None, 0) == Q.QS_EINVAL
