@@ -541,6 +541,13 @@ def main():
         if k[0] in ("h", "u"):
             per_target.setdefault(k[1], []).extend(v)
     cu_t = [d for k, v in durations.items() if k[0] == "cu" for d in v]
+    # controls inside a 128-byte line (unit bit < 3: control qubit < 3 at
+    # complex128, < 4 at complex64) make every line hold both halves, so the
+    # hardware moves the whole state: at most half the peak in algorithmic
+    # bytes.  Reported apart from the other pairs.
+    line_bits = 3 if args.dtype == "c128" else 4
+    cu_low = [d for k, v in durations.items() if k[0] == "cu" and k[1] < line_bits for d in v]
+    cu_reg = [d for k, v in durations.items() if k[0] == "cu" and k[1] >= line_bits for d in v]
     circ_t = durations[("circuit",)]
     probs_t = durations[("probs",)]
     mean_1q = statistics.fmean(one_q)
@@ -580,6 +587,11 @@ def main():
             "mean_launch_ms": statistics.fmean(cu_t) * 1e3,
             "step_s": statistics.fmean(cu_t) * len(pairs)},
     }
+    if cu_reg:
+        kernels["k_exchange/k_pair (controlled gate, control outside the 128-byte line)"] = {
+            "launches_per_step": len(cu_reg) / args.steps, "bytes_per_launch": S,
+            "mean_launch_ms": statistics.fmean(cu_reg) * 1e3,
+            "step_s": statistics.fmean(cu_reg) * len(cu_reg) / args.steps}
     for v in kernels.values():
         v["achieved_GBps"] = round(v["bytes_per_launch"] / (v["mean_launch_ms"] * 1e-3) / 1e9, 1)
         v["frac"] = round(v["achieved_GBps"] / PEAK_HBM_GBPS, 4)
@@ -619,6 +631,9 @@ def main():
         "detail": {
             "one_qubit_GBps_by_target": {str(k): round(v, 1) for k, v in sorted(tgt_gbps.items())},
             "one_qubit_GBps_min": round(min(tgt_gbps.values()), 1),
+            "cu_GBps_control_outside_line": round(S / statistics.fmean(cu_reg) / 1e9, 1) if cu_reg else None,
+            "cu_GBps_control_inside_line": round(S / statistics.fmean(cu_low) / 1e9, 1) if cu_low else None,
+            "cu_pairs_control_inside_line": len(cu_low) // max(1, args.steps),
             "cu_GBps_min_median_max": [round(cu_gbps[0], 1), round(statistics.median(cu_gbps), 1),
                                        round(cu_gbps[-1], 1)],
             "circuit_ms": round(statistics.median(circ_t) * 1e3, 3),
