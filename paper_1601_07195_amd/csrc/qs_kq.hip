@@ -9,10 +9,12 @@
 // matrix entries (uniform: scalar loads), and is stored where it was read.
 // Bytes: 2 * 2^n * b per gate, like a single-qubit gate; arithmetic 8 * 2^k
 // flop per amplitude, so k <= 4 stays HBM-bound at complex128 and k = 5
-// approaches the FP64 vector rate.
+// approaches the FP64 vector rate: complex128 k = 5 therefore runs as a
+// dense real contraction on the FP64 matrix cores (k_apply_kq_mfma).
 #include <string.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "qs_device.h"
 #include "qs_internal.h"
@@ -20,6 +22,8 @@
 namespace qs {
 
 constexpr int kKqBlock = 256;
+
+typedef double d4 __attribute__((ext_vector_type(4)));
 
 struct KqArgs {
   uint64_t ngroups;
@@ -130,6 +134,76 @@ k_apply_kq_lds(T* __restrict__ a, const R* __restrict__ u, KqLdsArgs A) {
   }
 }
 
+// complex128, k = 5 (the template also takes k = 4, where the vector
+// kernels measure faster): the gate as a dense real contraction on the FP64
+// matrix cores.  With D = 2^k members per group, the 2D x 2D real matrix
+// M = [[Re u, -Im u], [Im u, Re u]] maps (Re v, Im v) of a group to those
+// of u v.  A wave applies M to 16 groups at once: C (2D x 16) = M B, as
+// 2D/16 row blocks x 2D/4 steps of v_mfma_f64_16x16x4 (A: a 16 x 4 block of
+// M, lane i + 16 kk holding A[i][kk]; B: 4 x 16, lane jj + 16 kk holding
+// B[kk][jj]; C: lane jj + 16 (i % 4) holding C[i][jj] as item i / 4).  Lane
+// l works on group l % 16 and, with q = l / 16, loads members q, q + 4, ...
+// (row 4 ks + q of B is part (4 ks + q) / D of member (4 ks + q) % D), and
+// stores members 16 mb + q + 4 i (rows of C's block mb).  M's blocks are staged once
+// per workgroup in LDS in operand order: one conflict-free 8-byte LDS load
+// per lane feeds each MFMA.  Loads of 16 consecutive groups cover whole
+// lines whatever the targets, so no LDS tile of the state is needed.
+constexpr int kKqMfmaBlock = 256;
+
+struct KqMfmaArgs {
+  uint64_t nbatches;           // batches of 16 groups
+  int32_t spos[QS_KQ_MAX];     // target positions, ascending
+  int32_t tpos[QS_KQ_MAX];     // target of bit j of a member index
+};
+
+template <int K>
+__device__ __forceinline__ uint64_t kq_member_off(int r, const KqMfmaArgs& A) {
+  uint64_t o = 0;
+#pragma unroll
+  for (int t = 0; t < K; ++t) o |= (uint64_t)((r >> t) & 1) << A.tpos[t];
+  return o;
+}
+
+template <int K>
+__global__ void __launch_bounds__(kKqMfmaBlock)
+k_apply_kq_mfma(d2* __restrict__ a, const double* __restrict__ frag, KqMfmaArgs A) {
+  constexpr int D = 1 << K, M = 2 * D, MB = M / 16, KS = M / 4, NV = D / 4;
+  __shared__ double sa[MB * KS * 64];
+  for (int i = threadIdx.x; i < MB * KS * 64; i += kKqMfmaBlock) sa[i] = frag[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, j = lane & 15, q = lane >> 4;
+  uint64_t ld[NV], st[NV];
+#pragma unroll
+  for (int s = 0; s < NV; ++s) {
+    ld[s] = kq_member_off<K>(q + 4 * s, A);
+    st[s] = kq_member_off<K>(16 * (s / 4) + q + 4 * (s % 4), A);
+  }
+  const uint64_t nw = (uint64_t)gridDim.x * (kKqMfmaBlock / 64);
+  for (uint64_t bt = (uint64_t)blockIdx.x * (kKqMfmaBlock / 64) + threadIdx.x / 64; bt < A.nbatches;
+       bt += nw) {
+    uint64_t base = bt * 16 + j;
+#pragma unroll
+    for (int t = 0; t < K; ++t) base = insert0(base, A.spos[t]);
+    d2 v[NV];
+#pragma unroll
+    for (int s = 0; s < NV; ++s) v[s] = gload<true>(a + (base | ld[s]));
+    d4 acc[MB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) acc[mb] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const double b = ks < NV ? v[ks].x : v[ks - NV].y;
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+        acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[(mb * KS + ks) * 64 + lane], b, acc[mb], 0, 0, 0);
+    }
+    // real rows in blocks 0 .. MB/2 - 1, the imaginary rows MB/2 blocks later
+#pragma unroll
+    for (int s = 0; s < NV; ++s)
+      gstore<true>(a + (base | st[s]), d2{acc[s / 4][s % 4], acc[s / 4 + MB / 2][s % 4]});
+  }
+}
+
 template <typename R, typename T>
 static void go_kq_lds(StateImpl* s, int k, const R* u, const KqLdsArgs& A, unsigned grid) {
   T* a = (T*)s->ptr;
@@ -168,6 +242,42 @@ Status launch_apply_kq(StateImpl* s, int k, const int32_t* targets, const double
   for (int j = 0; j < k; ++j) sp[j] = targets[j];
   std::sort(sp, sp + k);
   for (int j = 0; j < k; ++j) A.spos[j] = sp[j];
+  if (s->dtype == QS_C128 && k == 5 && s->n - k >= 4) {
+    // M = [[Re u, -Im u], [Im u, Re u]] in MFMA operand order:
+    // frag[(mb * KS + ks) * 64 + l] = M[16 mb + l % 16][4 ks + l / 16]
+    const int M = 2 * D, MB = M / 16, KS = M / 4;
+    std::vector<double> frag((size_t)MB * KS * 64);
+    auto mval = [&](int row, int col) {
+      const int r = row % D, c = col % D;
+      const double re = u[2 * (r * D + c)], im = u[2 * (r * D + c) + 1];
+      if ((row < D) == (col < D)) return re;
+      return row < D ? -im : im;
+    };
+    for (int mb = 0; mb < MB; ++mb)
+      for (int ks = 0; ks < KS; ++ks)
+        for (int l = 0; l < 64; ++l)
+          frag[((size_t)mb * KS + ks) * 64 + l] = mval(16 * mb + l % 16, 4 * ks + l / 16);
+    Status st = upload_table(s, frag.data(), frag.size() * sizeof(double));
+    if (!st.good()) return st;
+    KqMfmaArgs B;
+    memset(&B, 0, sizeof(B));
+    B.nbatches = A.ngroups / 16;
+    for (int j = 0; j < k; ++j) {
+      B.spos[j] = sp[j];
+      B.tpos[j] = targets[j];
+    }
+    const uint64_t want = (B.nbatches + kKqMfmaBlock / 64 - 1) / (kKqMfmaBlock / 64);
+    // about five workgroups per compute unit (the LDS holds five copies of M)
+    const uint64_t cus = s->cus > 0 ? (uint64_t)s->cus : 256;
+    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(want, cus * 5));
+    if (k == 4)
+      hipLaunchKernelGGL((k_apply_kq_mfma<4>), dim3(grid), dim3(kKqMfmaBlock), 0, s->stream, (d2*)s->ptr,
+                         (const double*)s->table.ptr, B);
+    else
+      hipLaunchKernelGGL((k_apply_kq_mfma<5>), dim3(grid), dim3(kKqMfmaBlock), 0, s->stream, (d2*)s->ptr,
+                         (const double*)s->table.ptr, B);
+    return hip_status(hipGetLastError(), "apply_kq (mfma)");
+  }
   // the matrix in the compute precision, through the state's table buffer
   const size_t nval = 2 * (size_t)D * D;
   Status st;

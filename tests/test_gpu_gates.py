@@ -229,6 +229,23 @@ def test_apply_kq_vs_oracle(Q, name, n, k):
         assert np.abs(st.numpy() - ref).max() <= tol, (targets, trial)
 
 
+@pytest.mark.parametrize("n", [9, 10, 14])
+def test_apply_kq_five_qubits_matrix_core_path(Q, n):
+    """complex128 five-qubit gates run on the FP64 matrix cores from n = 9
+    (one batch of 16 groups) up: lowest, highest, reversed and random target
+    orders against the oracle."""
+    rng = np.random.default_rng(1100 + n)
+    cases = [[0, 1, 2, 3, 4], list(range(n - 5, n)), [4, 3, 2, 1, 0], [n - 1, 0, n // 2 + 1, 2, 4]]
+    cases.append([int(t) for t in rng.choice(n, 5, replace=False)])
+    for targets in cases:
+        u = _haar_dim(32, rng)
+        psi = random_state(n, rng)
+        st = to_gpu_state(Q, psi, Q.QS_C128)
+        st.apply_kq(targets, u)
+        ref = O.apply_kq(psi.copy(), n, targets, u)
+        assert np.abs(st.numpy() - ref).max() <= 1e-13, targets
+
+
 def test_apply_kq_equals_single_qubit_gates(Q):
     """A Kronecker product of 2x2 gates applied as one block equals the
     same gates applied one by one through qs_apply_1q."""
