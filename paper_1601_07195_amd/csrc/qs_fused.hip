@@ -275,7 +275,8 @@ __device__ __forceinline__ void run_ops(typename LdsAmp<R>::T* a, typename LdsAm
     if (RUNS && kind == kOpPhaseRun) {  // forward passes that hold runs only
       // the product of the run's phases, per lane: entry e contributes its
       // d1 where its control (none, a thread bit or a bit outside the tile)
-      // is 1; then the target-bit-1 amplitudes are scaled once
+      // is 1; then the target-bit-1 amplitudes (target on a register bit, a
+      // thread bit or outside the tile) are scaled once
       R pr = (R)1, pi = (R)0;
       for (int e = 1; e <= aux; ++e) {
         const FOp* en = ops + uniform(oi + e);
@@ -287,7 +288,7 @@ __device__ __forceinline__ void run_ops(typename LdsAmp<R>::T* a, typename LdsAm
         pi = pr * di + pi * dr;
         pr = t;
       }
-      diag_tile<R, NREG>(a, (R)1, (R)0, pr, pi, kInReg, tgt & 255, -1, true, true, base);
+      diag_tile<R, NREG>(a, (R)1, (R)0, pr, pi, tgt >> 8, tgt & 255, -1, true, true, base);
       oi += aux;
       nxt = ops[uniform(oi + 1)];
       continue;

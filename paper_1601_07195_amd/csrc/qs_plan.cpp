@@ -422,52 +422,70 @@ void plan_gates(int n, int dtype, const std::vector<XGate>& gates, bool fuse, Pl
       cur = load;
     }
     p.map_store = (int)out->maps.size() - 1;
-    // ---- phase runs: consecutive phase ops (d0 = 1, no gradient slot, no
-    // register control) on the same register target become one run header
-    // followed by their entries (diagonal ops commute, so the product is
-    // exact up to rounding).  Forward passes only: the adjoint kernels have
-    // no registers to spare for it.
+    // ---- phase runs.  Phase ops (diagonal, d0 = 1, no gradient slot)
+    // commute with each other, so a block of consecutive ones may be
+    // reordered freely.  A controlled phase is symmetric in its two qubits,
+    // so each takes as target the qubit held closest (register, then thread
+    // bit, then outside the tile) and as control the other.  The block is
+    // then sorted by target, and the ops on one target whose control is not
+    // a register bit become one run header followed by their entries: the
+    // kernel multiplies their phases per lane and scales the tile once.
+    // Forward passes only: the adjoint kernels have no registers to spare
+    // for it.
     if (!grad) {
-      auto member = [&](const FOp& o) {
-        return (o.kind & 255) == kOpDiag && o.aux < 0 && o.m[0] == 1.0 && o.m[1] == 0.0 &&
-               (o.tgt >> 8) == kInReg && (o.ctl >> 8) != kInReg;
+      auto is_phase = [&](const FOp& o) {
+        return (o.kind & 255) == kOpDiag && o.aux < 0 && o.m[0] == 1.0 && o.m[1] == 0.0;
       };
+      auto rank = [](int32_t spec) { return spec >> 8; };  // kInReg < kInThread < kOutside
       std::vector<FOp> nops;
       std::vector<OpMeta> nmeta;
       size_t i = (size_t)p.op_first;
       while (i < out->ops.size()) {
-        size_t j = i;
-        if (member(out->ops[i]))
-          while (j + 1 < out->ops.size() && member(out->ops[j + 1]) &&
-                 out->ops[j + 1].tgt == out->ops[i].tgt)
-            ++j;
-        if (j > i) {
-          FOp h;
-          std::memset(&h, 0, sizeof(h));
-          h.kind = kOpPhaseRun;
-          h.tgt = out->ops[i].tgt;
-          h.ctl = make_spec(kNoBit, 0);
-          h.aux = (int)(j - i + 1);
-          nops.push_back(h);
-          OpMeta hm = meta[i];
-          hm.remap = true;  // never a merge target
-          hm.mergeable = false;
-          nmeta.push_back(hm);
-          for (size_t k = i; k <= j; ++k) {
-            FOp e = out->ops[k];
-            e.kind = kOpPhaseEntry;
-            nops.push_back(e);
-            OpMeta em = meta[k];
-            em.remap = true;
-            em.mergeable = false;
-            nmeta.push_back(em);
-          }
-          i = j + 1;
+        if (!is_phase(out->ops[i])) {
+          nops.push_back(out->ops[i]);
+          nmeta.push_back(meta[i]);
+          ++i;
           continue;
         }
-        nops.push_back(out->ops[i]);
-        nmeta.push_back(meta[i]);
-        ++i;
+        size_t j = i;
+        while (j < out->ops.size() && is_phase(out->ops[j])) ++j;
+        std::vector<FOp> blk(out->ops.begin() + i, out->ops.begin() + j);
+        for (FOp& o : blk)
+          if (rank(o.ctl) != kNoBit && rank(o.ctl) < rank(o.tgt)) std::swap(o.tgt, o.ctl);
+        std::stable_sort(blk.begin(), blk.end(), [](const FOp& a, const FOp& b) { return a.tgt < b.tgt; });
+        auto member = [&](const FOp& o) { return rank(o.ctl) != kInReg; };
+        size_t a = 0;
+        while (a < blk.size()) {
+          size_t b = a;
+          if (member(blk[a]))
+            while (b + 1 < blk.size() && member(blk[b + 1]) && blk[b + 1].tgt == blk[a].tgt) ++b;
+          OpMeta om;
+          om.remap = true;  // never a merge target
+          om.mergeable = false;
+          om.target = om.control = -1;
+          om.fp.nq = 0;
+          if (b > a) {
+            FOp h;
+            std::memset(&h, 0, sizeof(h));
+            h.kind = kOpPhaseRun;
+            h.tgt = blk[a].tgt;
+            h.ctl = make_spec(kNoBit, 0);
+            h.aux = (int)(b - a + 1);
+            nops.push_back(h);
+            nmeta.push_back(om);
+            for (size_t k = a; k <= b; ++k) {
+              FOp e = blk[k];
+              e.kind = kOpPhaseEntry;
+              nops.push_back(e);
+              nmeta.push_back(om);
+            }
+          } else {
+            nops.push_back(blk[a]);
+            nmeta.push_back(om);
+          }
+          a = b + 1;
+        }
+        i = j;
       }
       out->ops.resize((size_t)p.op_first);
       meta.resize((size_t)p.op_first);
