@@ -63,7 +63,7 @@ k_probabilities(const T* __restrict__ a, int n, uint64_t nchunks, double* __rest
       const uint64_t i = base + (uint64_t)r * kBlock + threadIdx.x;
       double p = 0.0;
       if (i < N) {
-        p = norm2_of(a[i]);
+        p = norm2_of(gload<true>(a + i));  // streamed: read once
         if (FULL) full[i] = p;
       }
       s += p;
@@ -130,7 +130,7 @@ k_probabilities_c64(const f4* __restrict__ a, int n, uint64_t nchunks, double* _
       const uint64_t u = base + (uint64_t)r * kBlock + threadIdx.x;
       double p = 0.0;
       if (u < NU) {
-        const f4 v = a[u];
+        const f4 v = gload<true>(a + u);  // streamed: read once
         const double p0 = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
         const double p1 = (double)v.z * (double)v.z + (double)v.w * (double)v.w;
         if (FULL) {  // full is only 8-byte aligned
