@@ -236,6 +236,37 @@ __device__ __forceinline__ void diag_tile(T* a, R d0r, R d0i, R d1r, R d1i, int 
   }
 }
 
+// Gradient partials are summed over each 16-lane row of a wave with four
+// DPP steps (row mirror, half-row mirror, two quad permutations: plain
+// VALU moves, no LDS crossbar traffic); every lane ends with its row's sum,
+// added in a fixed order.  The first lane of each row adds it to its own
+// accumulator entry, kAdjRows per gradient slot and workgroup.
+constexpr int kAdjRows = kFuseBlock / 16;
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+__device__ __forceinline__ double row_sum16(double v) {
+  v += dpp_f64<0x140>(v);  // row_mirror: lane i + lane 15 - i
+  v += dpp_f64<0x141>(v);  // row_half_mirror: within each half-row
+  v += dpp_f64<0x1B>(v);   // quad_perm [3, 2, 1, 0]
+  v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  return v;
+}
+
+// A slot's kAdjRows row sums, added in row order.
+__device__ __forceinline__ double adj_slot_sum(const double* rows) {
+  double t = 0.0;
+#pragma unroll
+  for (int r = 0; r < kAdjRows; ++r) t += rows[r];
+  return t;
+}
+
 // Apply ops[0 .. nops) to the register tile(s).  `base` is the tile's
 // global index base (bits outside the tile).  The op index goes through
 // readfirstlane, so op records and mappings are fetched with scalar loads
@@ -245,7 +276,7 @@ __device__ __forceinline__ void diag_tile(T* a, R d0r, R d0i, R d1r, R d1i, int 
 //
 // ADJ: a second tile (lambda) receives every gate too, and ops with a
 // gradient slot first add Im<lambda|P|psi> (P = the rotation's generator,
-// X/Y on register pairs, Z by the sign of the target bit) to the wave's LDS
+// X/Y on register pairs, Z by the sign of the target bit) to its row's LDS
 // accumulator of that slot.
 template <typename R, int NREG, bool ADJ, bool RUNS = false>
 __device__ __forceinline__ void run_ops(typename LdsAmp<R>::T* a, typename LdsAmp<R>::T* l,
@@ -310,8 +341,8 @@ __device__ __forceinline__ void run_ops(typename LdsAmp<R>::T* a, typename LdsAm
       }
       if constexpr (ADJ) {
         if (aux >= 0) {  // rotation (never controlled): gradient before the inverse
-          const double g = wave_sum(reg_grad_any<NREG>(a, l, pauli, tgt));
-          if ((threadIdx.x & 63) == 0) acc[aux * 4 + (threadIdx.x >> 6)] += g;
+          const double g = row_sum16(reg_grad_any<NREG>(a, l, pauli, tgt));
+          if ((threadIdx.x & 15) == 0) acc[aux * kAdjRows + (threadIdx.x >> 4)] += g;
         }
       }
       if (cw == kInThread) {
@@ -351,8 +382,8 @@ __device__ __forceinline__ void run_ops(typename LdsAmp<R>::T* a, typename LdsAm
             const double t = im_conj_mul(l[r].x, l[r].y, a[r].x, a[r].y);
             g += bit ? -t : t;
           }
-          g = wave_sum(g);
-          if ((threadIdx.x & 63) == 0) acc[aux * 4 + (threadIdx.x >> 6)] += g;
+          g = row_sum16(g);
+          if ((threadIdx.x & 15) == 0) acc[aux * kAdjRows + (threadIdx.x >> 4)] += g;
         }
       }
       const bool phase = (kw >> 16) & 1;
@@ -431,8 +462,8 @@ k_fused_adj_c128(d2* __restrict__ psi, d2* __restrict__ lam, FusedArgs A,
                  double* __restrict__ part) {
   constexpr int RA = 1 << NREG;
   __shared__ d2 lds[RA * kFuseBlock];
-  __shared__ double acc[kAdjMaxSlots * 4];
-  for (int i = threadIdx.x; i < kAdjMaxSlots * 4; i += kFuseBlock) acc[i] = 0.0;
+  __shared__ double acc[kAdjMaxSlots * kAdjRows];
+  for (int i = threadIdx.x; i < kAdjMaxSlots * kAdjRows; i += kFuseBlock) acc[i] = 0.0;
   __syncthreads();
   d2 t[RA], l[RA];
   const uint64_t tl = thr_global_off(A.ld_thr), ts = thr_global_off(A.st_thr);
@@ -454,8 +485,7 @@ k_fused_adj_c128(d2* __restrict__ psi, d2* __restrict__ lam, FusedArgs A,
   }
   __syncthreads();
   for (int sl = threadIdx.x; sl < A.ngrad; sl += kFuseBlock)
-    part[(size_t)sl * gridDim.x + blockIdx.x] =
-        acc[sl * 4] + acc[sl * 4 + 1] + acc[sl * 4 + 2] + acc[sl * 4 + 3];
+    part[(size_t)sl * gridDim.x + blockIdx.x] = adj_slot_sum(acc + sl * kAdjRows);
 }
 
 template <int NREG>
@@ -465,8 +495,8 @@ k_fused_adj_c64(f4* __restrict__ psi, f4* __restrict__ lam, FusedArgs A,
                 double* __restrict__ part) {
   constexpr int RA = 1 << NREG;
   __shared__ f2 lds[RA * kFuseBlock];
-  __shared__ double acc[kAdjMaxSlots * 4];
-  for (int i = threadIdx.x; i < kAdjMaxSlots * 4; i += kFuseBlock) acc[i] = 0.0;
+  __shared__ double acc[kAdjMaxSlots * kAdjRows];
+  for (int i = threadIdx.x; i < kAdjMaxSlots * kAdjRows; i += kFuseBlock) acc[i] = 0.0;
   __syncthreads();
   f2 t[RA], l[RA];
   const uint64_t tl = thr_global_off(A.ld_thr), ts = thr_global_off(A.st_thr);
@@ -491,8 +521,7 @@ k_fused_adj_c64(f4* __restrict__ psi, f4* __restrict__ lam, FusedArgs A,
   }
   __syncthreads();
   for (int sl = threadIdx.x; sl < A.ngrad; sl += kFuseBlock)
-    part[(size_t)sl * gridDim.x + blockIdx.x] =
-        acc[sl * 4] + acc[sl * 4 + 1] + acc[sl * 4 + 2] + acc[sl * 4 + 3];
+    part[(size_t)sl * gridDim.x + blockIdx.x] = adj_slot_sum(acc + sl * kAdjRows);
 }
 
 // Host: device tables of a plan's mappings.
