@@ -143,7 +143,9 @@ int qs_apply_cu(qs_state* s, int c, int t, const double* q);
  *   u        host, 2^k x 2^k complex entries, row-major, each (re, im):
  *            2 * 4^k doubles (a complex64 state uses them rounded to float)
  * Asynchronous on the state's stream; the matrix is copied before return.
- * u is not checked for unitarity.
+ * u is not checked for unitarity.  complex128 gates on five qubits run on
+ * the FP64 matrix cores (the gate as a dense real contraction), the others
+ * on the vector units.
  * Errors: QS_EINVAL (k out of range, a target out of range or repeated,
  * NULL), QS_ENOMEM, QS_EHIP.
  */
@@ -172,7 +174,7 @@ int qs_run(qs_state* s, const qs_op* ops, int nops, const double* theta,
  * bit perm[q] equals bit q of i, for every q.  A swap of two qubits is the
  * permutation that exchanges them.
  *   perm  host, n int32: a permutation of 0 .. n-1 (copied before return)
- * Runs as at most two passes of disjoint qubit swaps, each one or two
+ * Runs as at most two passes of disjoint qubit swaps, each of one to three
  * launches: swaps of two qubits above the 1 KiB block bits (6 for complex128,
  * 7 for complex64) move only the blocks that change place, 2 (1 - 2^-k) S
  * bytes for k swaps (S = the state's bytes); swaps that touch a block bit
