@@ -122,7 +122,9 @@ def measured_traffic(kernel: str, workload: str):
 
 def cpu_baseline(n_gpu: int, u, pairs, args):
     """The CPU oracle, as it stands, on a bounded sample of the same
-    per-gate workload: H and U on four targets and two controlled-U gates."""
+    per-gate workload: H and U on every target and eight controlled-U gates
+    on the host's threads (at most 16), then H on the lowest and highest
+    target on one thread."""
     import numpy as np
 
     import circuits as C
@@ -139,31 +141,37 @@ def cpu_baseline(n_gpu: int, u, pairs, args):
                 n -= 1
         except Exception:
             n = min(n, 26)
-    O.set_threads(threads)
     psi = O.basis_state(n)
-    targets = sorted({0, n // 3, (2 * n) // 3, n - 1})
     gates = []
-    for k in targets:
+    for k in range(n):
         gates.append(("1q", k, C.H_GATE))
         gates.append(("1q", k, u))
-    for c, t in pairs[:2]:
+    for c, t in pairs[:8]:
         gates.append(("cu", (c % n, t % n) if c % n != t % n else (0, n - 1), u))
     S = (1 << n) * 16
-    nbytes = 0
-    t0 = time.perf_counter()
-    for kind, q, m in gates:
-        if kind == "1q":
-            O.apply_1q(psi, n, q, m)
-            nbytes += 2 * S
-        else:
-            O.apply_cu(psi, n, q[0], q[1], m)
-            nbytes += S
-    dt = time.perf_counter() - t0
+
+    def run(gs):
+        nbytes = 0
+        t0 = time.perf_counter()
+        for kind, q, m in gs:
+            if kind == "1q":
+                O.apply_1q(psi, n, q, m)
+                nbytes += 2 * S
+            else:
+                O.apply_cu(psi, n, q[0], q[1], m)
+                nbytes += S
+        return nbytes, time.perf_counter() - t0
+
+    O.set_threads(threads)
+    nbytes, dt = run(gates)
     O.set_threads(1)
+    nb1, dt1 = run([("1q", 0, C.H_GATE), ("1q", n - 1, C.H_GATE)])
     return {
         "value": round(nbytes / dt / 1e9, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
-        "sample": f"complex128 n={n}: H and Haar U on targets {targets} + 2 controlled-U, "
-                  f"{len(gates)} gates, {dt:.2f} s",
+        "sample": f"complex128 n={n}: H and Haar U on all {n} targets + {len(gates) - 2 * n} "
+                  f"controlled-U, {len(gates)} gates, {dt:.2f} s",
+        "one_core_GBps": round(nb1 / dt1 / 1e9, 3),
+        "one_core_sample": f"H on targets 0 and {n - 1}, {dt1:.2f} s",
     }
 
 
