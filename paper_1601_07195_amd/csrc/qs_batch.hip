@@ -294,6 +294,28 @@ __device__ __forceinline__ double blk_grad(const T* x, const T* y) {
   }
   return g;
 }
+// Wave total of a gradient partial with DPP moves only (no LDS crossbar):
+// row sums (row mirror, half-row mirror, two quad permutations), then the
+// last lane of rows 0 and 2 added into rows 1 and 3, and the last lane of
+// row 1 into rows 2 and 3.  Lane 63 ends with the total, added in a fixed
+// order; rows left out of a step take 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROWS, 0xF, false);
+  return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+__device__ __forceinline__ double wave_total_last_lane(double v) {
+  v += dpp_f64<0x140, 0xF>(v);  // row_mirror
+  v += dpp_f64<0x141, 0xF>(v);  // row_half_mirror
+  v += dpp_f64<0x1B, 0xF>(v);   // quad_perm [3, 2, 1, 0]
+  v += dpp_f64<0xB1, 0xF>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_f64<0x142, 0xA>(v);  // row_bcast15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xC>(v);  // row_bcast31 into rows 2 and 3
+  return v;
+}
+
 template <typename T>
 __device__ __forceinline__ double blk_grad_any(const T* x, const T* y, int pauli, int rt) {
   double g;
@@ -346,11 +368,10 @@ __device__ __forceinline__ void run_block(T* a, T* l, int m, const BBlk& bk, con
       rec_mat<R>(rec, REV, q);
       if constexpr (REV) {
         if (rec.rot >= 0) {
-          double g = blk_grad_any(x, y, rec.kind - QS_OP_RX + 1, rt);
-          g = wave_sum(g);
+          const double g = wave_total_last_lane(blk_grad_any(x, y, rec.kind - QS_OP_RX + 1, rt));
           // no-return atomic: the wave does not wait for the update; one lane
           // of one wave owns the slot, so the adds land in program order
-          if (lane == 0) atomicAdd(&gacc[rec.rot * NW + wave], g);
+          if (lane == 63) atomicAdd(&gacc[rec.rot * NW + wave], g);
         }
         blk_gate_any(y, q, rt, rc, rec.form);
       }
