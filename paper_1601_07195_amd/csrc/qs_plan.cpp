@@ -111,9 +111,6 @@ struct OpMeta {
   Footprint fp;
 };
 
-// Global qubit held by tile bit tb.
-inline int tile_qubit(int tb, int L, const std::vector<int>& hq) { return tb < L ? tb : hq[tb - L]; }
-
 struct Mapping {
   int thr[8];
   int reg[5];
@@ -209,8 +206,6 @@ void plan_gates(int n, int dtype, const std::vector<XGate>& gates, bool fuse, Pl
     for (int g : take) done[g] = 1;
     while (start < N && done[start]) ++start;
 
-    int nondiag = 0;
-    for (int g : take) nondiag += !diag[g];
     if (take.size() == 1 && allow_single) {  // one gate: the streaming kernels are as cheap or cheaper
       stream_pass(take[0]);
       continue;
