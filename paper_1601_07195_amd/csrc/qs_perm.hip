@@ -50,7 +50,10 @@ k_swap_blocks(u64x2* __restrict__ a, BlockSwapArgs A) {
   const uint64_t nwaves = (uint64_t)gridDim.x * W;
   const uint64_t lane = threadIdx.x & 63;
   const uint64_t nsteps = A.units / (64 * kSwapBlocks);
-  for (uint64_t c = (uint64_t)blockIdx.x * W + threadIdx.x / 64; c < nsteps; c += nwaves) {
+  // the wave index through readfirstlane: block indices, partners and the
+  // move test are then scalar, and the branch is uniform
+  const uint64_t w0 = (uint64_t)blockIdx.x * W + (uint64_t)__builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  for (uint64_t c = w0; c < nsteps; c += nwaves) {
     uint64_t hs[kSwapBlocks], xs[kSwapBlocks];
     u64x2 vp[kSwapBlocks], vq[kSwapBlocks];
 #pragma unroll
