@@ -108,6 +108,21 @@ __device__ __forceinline__ void reg_gate(T* a, const Mat<R>& q) {
   }
 }
 
+// The same pairs for a real matrix (RY, X, H: half the arithmetic).
+template <int K, int CR, int RA, typename T, typename R>
+__device__ __forceinline__ void reg_gate_real(T* a, const Mat<R>& q) {
+#pragma unroll
+  for (int r = 0; r < RA; ++r) {
+    if (r & (1 << K)) continue;
+    if (CR >= 0 && !((r >> CR) & 1)) continue;
+    T& x = a[r];
+    T& y = a[r | (1 << K)];
+    const R xr = x.x, xi = x.y, yr = y.x, yi = y.y;
+    x = T{q.r[0] * xr + q.r[1] * yr, q.r[0] * xi + q.r[1] * yi};
+    y = T{q.r[2] * xr + q.r[3] * yr, q.r[2] * xi + q.r[3] * yi};
+  }
+}
+
 // Im<lambda|P|psi> over the register pairs of bit K (P = X or Y).
 template <int K, int RA, typename T>
 __device__ __forceinline__ double reg_grad(const T* a, const T* l, int pauli) {
@@ -159,6 +174,37 @@ __device__ __forceinline__ void reg_gate_any(T* a, const Mat<R>& q, int cr, int 
     QS_REG_GATE(3, -1) QS_REG_GATE(3, 0) QS_REG_GATE(3, 1) QS_REG_GATE(3, 2)
 #undef QS_REG_GATE
     default: break;
+  }
+}
+
+template <typename R, int NREG, typename T>
+__device__ __forceinline__ void reg_real_any(T* a, const Mat<R>& q, int cr, int k) {
+  constexpr int RA = 1 << NREG;
+  switch (k * 8 + cr + 1) {
+#define QS_REG_REAL(K, CR)                                                  \
+  case K * 8 + CR + 1:                                                      \
+    if constexpr (K < NREG && CR < NREG) reg_gate_real<K, CR, RA>(a, q);   \
+    break;
+    QS_REG_REAL(0, -1) QS_REG_REAL(0, 1) QS_REG_REAL(0, 2) QS_REG_REAL(0, 3)
+    QS_REG_REAL(1, -1) QS_REG_REAL(1, 0) QS_REG_REAL(1, 2) QS_REG_REAL(1, 3)
+    QS_REG_REAL(2, -1) QS_REG_REAL(2, 0) QS_REG_REAL(2, 1) QS_REG_REAL(2, 3)
+    QS_REG_REAL(3, -1) QS_REG_REAL(3, 0) QS_REG_REAL(3, 1) QS_REG_REAL(3, 2)
+#undef QS_REG_REAL
+    default: break;
+  }
+}
+// A U op by the form of its matrix (each branch ends in its own empty asm
+// statement so that the optimiser keeps the bodies apart).  An exchange body
+// for X measured worse: its register renaming across the branches sent the
+// tiles to scratch memory.
+template <typename R, int NREG, typename T>
+__device__ __forceinline__ void reg_form_any(T* a, const Mat<R>& q, int cr, int k, int kw) {
+  if (kw & kUReal) {
+    reg_real_any<R, NREG>(a, q, cr, k);
+    asm volatile("; uform real");
+  } else {
+    reg_gate_any<R, NREG>(a, q, cr, k);
+    asm volatile("; uform general");
   }
 }
 
@@ -350,8 +396,8 @@ __device__ __forceinline__ void run_ops(typename LdsAmp<R>::T* a, typename LdsAm
           // two tiles: masking the lanes off costs less than per-lane
           // coefficients for both (measured)
           if (on) {
-            reg_gate_any<R, NREG>(a, q, -1, tgt);
-            reg_gate_any<R, NREG>(l, q, -1, tgt);
+            reg_form_any<R, NREG>(a, q, -1, tgt, kw);
+            reg_form_any<R, NREG>(l, q, -1, tgt, kw);
           }
         } else {
           Mat<R> ql;
@@ -364,8 +410,12 @@ __device__ __forceinline__ void run_ops(typename LdsAmp<R>::T* a, typename LdsAm
           reg_gate_any<R, NREG>(a, ql, -1, tgt);
         }
       } else {
-        reg_gate_any<R, NREG>(a, q, creg, tgt);
-        if constexpr (ADJ) reg_gate_any<R, NREG>(l, q, creg, tgt);
+        if constexpr (ADJ) {
+          reg_form_any<R, NREG>(a, q, creg, tgt, kw);
+          reg_form_any<R, NREG>(l, q, creg, tgt, kw);
+        } else {
+          reg_gate_any<R, NREG>(a, q, creg, tgt);
+        }
       }
     } else {  // diagonal
       if (cw == kOutside && !((base >> ci) & 1)) continue;  // per-tile predicate (uniform)
@@ -567,6 +617,13 @@ static Status upload_plan(StateImpl* s, const Plan& plan, const FuseGeom& G, con
   for (size_t i = 0; i < plan.ops.size(); ++i)
     if ((fo[i].kind & 255) == kOpDiag && fo[i].m[0] == 1.0 && fo[i].m[1] == 0.0)
       fo[i].kind |= kDiagPhase;
+  // U ops whose matrix is real (the adjoint kernels use the cheaper body;
+  // the forward kernels ignore the flag)
+  for (size_t i = 0; i < plan.ops.size(); ++i) {
+    const double* m = fo[i].m;
+    if ((fo[i].kind & 255) == kOpU && m[1] == 0.0 && m[3] == 0.0 && m[5] == 0.0 && m[7] == 0.0)
+      fo[i].kind |= kUReal;
+  }
   memcpy(blob.data() + ob, md.data(), mb);
   Status st = upload_table(s, blob.data(), blob.size());
   if (!st.good()) return st;

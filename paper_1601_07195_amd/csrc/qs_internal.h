@@ -159,6 +159,8 @@ enum FOpKind { kOpRemap = 0, kOpU = 1, kOpDiag = 2, kOpPhaseRun = 3, kOpPhaseEnt
 // FOp::kind bits 8..15: the Pauli generator of a gradient op; bit 16 on a
 // diagonal op: d0 = 1 (a phase), set when the plan is uploaded.
 constexpr int32_t kDiagPhase = 1 << 16;
+// A U op whose matrix has real entries, flagged at upload.
+constexpr int32_t kUReal = 1 << 17;
 struct FOp {
   int32_t kind;
   int32_t tgt;   // kOpU: register bit; kOpDiag: spec of the target; kOpRemap: new FMap index
