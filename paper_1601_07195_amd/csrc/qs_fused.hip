@@ -539,7 +539,7 @@ k_fused_adj_c128(d2* __restrict__ psi, d2* __restrict__ lam, FusedArgs A,
 }
 
 template <int NREG>
-__global__ void __launch_bounds__(kFuseBlock, 2)  // two waves per SIMD: at most 256 registers
+__global__ void __launch_bounds__(kFuseBlock, 3)  // three waves per SIMD, as for complex128
 k_fused_adj_c64(f4* __restrict__ psi, f4* __restrict__ lam, FusedArgs A,
                 const FOp* __restrict__ ops, const FMapDev* __restrict__ maps,
                 double* __restrict__ part) {
@@ -701,7 +701,7 @@ static int device_cus(StateImpl* s) {
   return s->cus;
 }
 
-constexpr int kAdjWgPerCu128 = 3, kAdjWgPerCu64 = 2;  // resident adjoint workgroups per CU
+constexpr int kAdjWgPerCu = 3;  // resident adjoint workgroups per CU (three waves per SIMD)
 
 Status run_adjoint_fused(StateImpl* s, StateImpl* lam, const std::vector<XGate>& rev,
                          std::vector<int>* rows, double** slot_sums_dev) {
@@ -714,8 +714,7 @@ Status run_adjoint_fused(StateImpl* s, StateImpl* lam, const std::vector<XGate>&
   if (!st.good()) return st;
   const uint64_t ntiles = 1ull << (s->n - G.T);
   const unsigned grid =
-      (unsigned)std::min<uint64_t>(ntiles, (uint64_t)device_cus(s) *
-                                          (s->dtype == QS_C128 ? kAdjWgPerCu128 : kAdjWgPerCu64));
+      (unsigned)std::min<uint64_t>(ntiles, (uint64_t)device_cus(s) * kAdjWgPerCu);
   const size_t nslots = plan.grad_rows.size();
   // reduction buffer: [slot][grid] partials, then nslots sums
   st = ensure_dev(s, s->red, (nslots * grid + nslots + 2) * sizeof(double));
