@@ -713,16 +713,22 @@ Status run_adjoint_fused(StateImpl* s, StateImpl* lam, const std::vector<XGate>&
   Status st = upload_plan(s, plan, G, &dops, &dmaps);
   if (!st.good()) return st;
   const uint64_t ntiles = 1ull << (s->n - G.T);
-  const unsigned grid =
-      (unsigned)std::min<uint64_t>(ntiles, (uint64_t)device_cus(s) * kAdjWgPerCu);
   const size_t nslots = plan.grad_rows.size();
-  // reduction buffer: [slot][grid] partials, then nslots sums
-  st = ensure_dev(s, s->red, (nslots * grid + nslots + 2) * sizeof(double));
+  // Up to 2^19 tiles, one workgroup per tile (a one-shot grid: the loads,
+  // arithmetic and stores of different workgroups overlap); each pass's
+  // partials [slot][tile] are summed right after it, so the buffer holds one
+  // pass.  Larger states use a persistent grid and one buffer for all passes.
+  const bool oneshot = ntiles <= (1ull << 19);
+  const unsigned grid = oneshot ? (unsigned)ntiles
+                                : (unsigned)std::min<uint64_t>(ntiles, (uint64_t)device_cus(s) * kAdjWgPerCu);
+  const size_t prow = oneshot ? (size_t)kAdjMaxSlots : nslots;
+  st = ensure_dev(s, s->red, (prow * grid + nslots + 2) * sizeof(double));
   if (!st.good()) return st;
   double* part = (double*)s->red.ptr;
+  double* sums = part + prow * grid;
   for (const Pass& p : plan.passes) {
     const FusedArgs A = pass_args(s, plan, p, G);
-    double* pp = part + (size_t)p.grad_first * grid;
+    double* pp = oneshot ? part : part + (size_t)p.grad_first * grid;
     if (s->dtype == QS_C128)
       hipLaunchKernelGGL((k_fused_adj_c128<3>), dim3(grid), dim3(kFuseBlock), 0, s->stream,
                          (d2*)s->ptr, (d2*)lam->ptr, A, dops + p.op_first, dmaps, pp);
@@ -731,9 +737,12 @@ Status run_adjoint_fused(StateImpl* s, StateImpl* lam, const std::vector<XGate>&
                          (f4*)s->ptr, (f4*)lam->ptr, A, dops + p.op_first, dmaps, pp);
     st = last_launch("fused adjoint pass");
     if (!st.good()) return st;
+    if (oneshot && p.ngrad > 0) {
+      st = launch_sum_rows(s, part, p.ngrad, (int)grid, sums + p.grad_first);
+      if (!st.good()) return st;
+    }
   }
-  double* sums = part + nslots * grid;
-  if (nslots > 0) {
+  if (!oneshot && nslots > 0) {
     st = launch_sum_rows(s, part, (int)nslots, (int)grid, sums);
     if (!st.good()) return st;
   }
