@@ -143,12 +143,17 @@ def test_oracle_threads_do_not_change_results():
     circ = C.random_circuit(n, 50, rng(12))
     O.set_threads(1)
     a = O.run(circ.ops, n)
+    perm = [int(x) for x in rng(13).permutation(n)]
+    u5 = _haar(32, rng(14))
+    a1 = O.permute_qubits(O.apply_kq(a.copy(), n, [0, 3, 7, 9, 13], u5), n, perm)
     O.set_threads(4)
     try:
         b = O.run(circ.ops, n)
+        b1 = O.permute_qubits(O.apply_kq(b.copy(), n, [0, 3, 7, 9, 13], u5), n, perm)
     finally:
         O.set_threads(1)
     assert np.array_equal(a, b)
+    assert np.array_equal(a1, b1)
 
 
 # ------------------------------------------------------------- probabilities
