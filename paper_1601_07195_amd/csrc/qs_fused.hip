@@ -354,17 +354,48 @@ __device__ __forceinline__ void run_ops(typename LdsAmp<R>::T* a, typename LdsAm
       // d1 where its control (none, a thread bit or a bit outside the tile)
       // is 1; then the target-bit-1 amplitudes (target on a register bit, a
       // thread bit or outside the tile) are scaled once
-      R pr = (R)1, pi = (R)0;
-      for (int e = 1; e <= aux; ++e) {
-        const FOp* en = ops + uniform(oi + e);
-        const int ec = en->ctl, ew = ec >> 8, eb = ec & 255;
+      // Entries are read four at a time (their scalar loads in flight
+      // together) into two product chains, even and odd entries, which are
+      // joined at the end.
+      auto factor = [&](int ec, double m6, double m7, R& fr, R& fi) {
+        const int ew = ec >> 8, eb = ec & 255;
         const bool eon = ew == kNoBit || (ew == kInThread ? (bool)((threadIdx.x >> eb) & 1)
                                                           : (bool)((base >> eb) & 1));
-        const R dr = eon ? (R)en->m[6] : (R)1, di = eon ? (R)en->m[7] : (R)0;
-        const R t = pr * dr - pi * di;
-        pi = pr * di + pi * dr;
-        pr = t;
+        fr = eon ? (R)m6 : (R)1;
+        fi = eon ? (R)m7 : (R)0;
+      };
+      auto mul_into = [](R& pr_, R& pi_, R dr, R di) {
+        const R t = pr_ * dr - pi_ * di;
+        pi_ = pr_ * di + pi_ * dr;
+        pr_ = t;
+      };
+      R pr = (R)1, pi = (R)0, qr = (R)1, qi = (R)0;
+      int e = 1;
+      for (; e + 3 <= aux; e += 4) {
+        int ec[4];
+        double m6[4], m7[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const FOp* en = ops + uniform(oi + e + j);
+          ec[j] = en->ctl;
+          m6[j] = en->m[6];
+          m7[j] = en->m[7];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          R dr, di;
+          factor(ec[j], m6[j], m7[j], dr, di);
+          if (j & 1) mul_into(qr, qi, dr, di);
+          else mul_into(pr, pi, dr, di);
+        }
       }
+      for (; e <= aux; ++e) {
+        const FOp* en = ops + uniform(oi + e);
+        R dr, di;
+        factor(en->ctl, en->m[6], en->m[7], dr, di);
+        mul_into(pr, pi, dr, di);
+      }
+      mul_into(pr, pi, qr, qi);
       diag_tile<R, NREG>(a, (R)1, (R)0, pr, pi, tgt >> 8, tgt & 255, -1, true, true, base);
       oi += aux;
       nxt = ops[uniform(oi + 1)];
