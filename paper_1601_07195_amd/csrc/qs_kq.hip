@@ -22,6 +22,10 @@
 namespace qs {
 
 constexpr int kKqBlock = 256;
+// Workgroup size of the direct kernel: 64 for k <= 2 (measured faster with
+// the highest targets), 256 above.
+template <int K>
+constexpr int kq_block() { return K <= 2 ? 64 : kKqBlock; }
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -40,11 +44,12 @@ __device__ __forceinline__ R ldc_r(const R* p) {
 }
 
 template <typename R, typename T, int K>
-__global__ void __launch_bounds__(kKqBlock)
+__global__ void __launch_bounds__(kq_block<K>())
 k_apply_kq(T* __restrict__ a, const R* __restrict__ u, KqArgs A) {
   constexpr int D = 1 << K;
-  const uint64_t stride = (uint64_t)gridDim.x * kKqBlock;
-  for (uint64_t g = (uint64_t)blockIdx.x * kKqBlock + threadIdx.x; g < A.ngroups; g += stride) {
+  constexpr int B = kq_block<K>();
+  const uint64_t stride = (uint64_t)gridDim.x * B;
+  for (uint64_t g = (uint64_t)blockIdx.x * B + threadIdx.x; g < A.ngroups; g += stride) {
     uint64_t base = g;
 #pragma unroll
     for (int j = 0; j < K; ++j) base = insert0(base, A.spos[j]);
@@ -217,15 +222,22 @@ static void go_kq_lds(StateImpl* s, int k, const R* u, const KqLdsArgs& A, unsig
   }
 }
 
+template <int K>
+static unsigned kq_grid(uint64_t ngroups) {
+  constexpr int B = kq_block<K>();
+  const uint64_t want = (ngroups + B - 1) / B;
+  return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(want, (1ull << 31) / B));
+}
+
 template <typename R, typename T>
-static void go_kq(StateImpl* s, int k, const R* u, const KqArgs& A, unsigned grid) {
+static void go_kq(StateImpl* s, int k, const R* u, const KqArgs& A) {
   T* a = (T*)s->ptr;
   switch (k) {
-    case 1: hipLaunchKernelGGL((k_apply_kq<R, T, 1>), dim3(grid), dim3(kKqBlock), 0, s->stream, a, u, A); break;
-    case 2: hipLaunchKernelGGL((k_apply_kq<R, T, 2>), dim3(grid), dim3(kKqBlock), 0, s->stream, a, u, A); break;
-    case 3: hipLaunchKernelGGL((k_apply_kq<R, T, 3>), dim3(grid), dim3(kKqBlock), 0, s->stream, a, u, A); break;
-    case 4: hipLaunchKernelGGL((k_apply_kq<R, T, 4>), dim3(grid), dim3(kKqBlock), 0, s->stream, a, u, A); break;
-    default: hipLaunchKernelGGL((k_apply_kq<R, T, 5>), dim3(grid), dim3(kKqBlock), 0, s->stream, a, u, A); break;
+    case 1: hipLaunchKernelGGL((k_apply_kq<R, T, 1>), dim3(kq_grid<1>(A.ngroups)), dim3(kq_block<1>()), 0, s->stream, a, u, A); break;
+    case 2: hipLaunchKernelGGL((k_apply_kq<R, T, 2>), dim3(kq_grid<2>(A.ngroups)), dim3(kq_block<2>()), 0, s->stream, a, u, A); break;
+    case 3: hipLaunchKernelGGL((k_apply_kq<R, T, 3>), dim3(kq_grid<3>(A.ngroups)), dim3(kq_block<3>()), 0, s->stream, a, u, A); break;
+    case 4: hipLaunchKernelGGL((k_apply_kq<R, T, 4>), dim3(kq_grid<4>(A.ngroups)), dim3(kq_block<4>()), 0, s->stream, a, u, A); break;
+    default: hipLaunchKernelGGL((k_apply_kq<R, T, 5>), dim3(kq_grid<5>(A.ngroups)), dim3(kq_block<5>()), 0, s->stream, a, u, A); break;
   }
 }
 
@@ -328,12 +340,10 @@ Status launch_apply_kq(StateImpl* s, int k, const int32_t* targets, const double
       go_kq_lds<float, f2>(s, k, (const float*)s->table.ptr, L, lgrid);
     return hip_status(hipGetLastError(), "apply_kq");
   }
-  const uint64_t want = (A.ngroups + kKqBlock - 1) / kKqBlock;
-  const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(want, (1ull << 31) / kKqBlock));
   if (s->dtype == QS_C128)
-    go_kq<double, d2>(s, k, (const double*)s->table.ptr, A, grid);
+    go_kq<double, d2>(s, k, (const double*)s->table.ptr, A);
   else
-    go_kq<float, f2>(s, k, (const float*)s->table.ptr, A, grid);
+    go_kq<float, f2>(s, k, (const float*)s->table.ptr, A);
   return hip_status(hipGetLastError(), "apply_kq");
 }
 
