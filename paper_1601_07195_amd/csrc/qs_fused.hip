@@ -328,7 +328,7 @@ template <typename R, int NREG, bool ADJ, bool RUNS = false>
 __device__ __forceinline__ void run_ops(typename LdsAmp<R>::T* a, typename LdsAmp<R>::T* l,
                                         typename LdsAmp<R>::T* lds, const FOp* __restrict__ ops,
                                         int nops, const FMapDev* __restrict__ maps,
-                                        uint64_t base, double* acc) {
+                                        uint64_t base, double* acc, uint64_t tile) {
   constexpr int RA = 1 << NREG;
   // The next op's record is fetched (scalar loads) while this op computes;
   // the table holds one spare record past every pass's last op.
@@ -351,9 +351,10 @@ __device__ __forceinline__ void run_ops(typename LdsAmp<R>::T* a, typename LdsAm
     }
     if (RUNS && kind == kOpPhaseRun) {  // forward passes that hold runs only
       // the product of the run's phases, per lane: entry e contributes its
-      // d1 where its control (none, a thread bit or a bit outside the tile)
-      // is 1; then the target-bit-1 amplitudes (target on a register bit, a
-      // thread bit or outside the tile) are scaled once
+      // d1 where its control (none or a thread bit) is 1, and the entries
+      // controlled outside the tile come as one product from the run's
+      // tables; then the target-bit-1 amplitudes (target on a register bit,
+      // a thread bit or outside the tile) are scaled once
       // Entries are read four at a time (their scalar loads in flight
       // together) into two product chains, even and odd entries, which are
       // joined at the end.
@@ -396,6 +397,16 @@ __device__ __forceinline__ void run_ops(typename LdsAmp<R>::T* a, typename LdsAm
         mul_into(pr, pi, dr, di);
       }
       mul_into(pr, pi, qr, qi);
+      if (op->m[2] != 0.0) {
+        // entries controlled outside the tile: their product by the tile
+        // index, from the run's two tables (low and high index bits)
+        const int lb = (int)op->m[1];
+        const double* tlo = (const double*)((const char*)maps + (size_t)op->m[0]);
+        const double* thi = tlo + 2 * ((size_t)1 << lb);
+        const uint64_t lo = tile & ((1ull << lb) - 1ull), hi = tile >> lb;
+        mul_into(pr, pi, (R)tlo[2 * lo], (R)tlo[2 * lo + 1]);
+        mul_into(pr, pi, (R)thi[2 * hi], (R)thi[2 * hi + 1]);
+      }
       diag_tile<R, NREG>(a, (R)1, (R)0, pr, pi, tgt >> 8, tgt & 255, -1, true, true, base);
       oi += aux;
       nxt = ops[uniform(oi + 1)];
@@ -500,7 +511,7 @@ k_fused_c128(d2* __restrict__ a, FusedArgs A, const FOp* __restrict__ ops,
     const uint64_t base = tile_base(tile, A);
 #pragma unroll
     for (int r = 0; r < RA; ++r) t[r] = gload<true>(a + (base | tl | reg_global_off<NREG>(A.ld_reg, r)));
-    run_ops<double, NREG, false, RUNS>(t, nullptr, lds, ops, A.nops, maps, base, nullptr);
+    run_ops<double, NREG, false, RUNS>(t, nullptr, lds, ops, A.nops, maps, base, nullptr, tile);
 #pragma unroll
     for (int r = 0; r < RA; ++r) gstore<true>(a + (base | ts | reg_global_off<NREG>(A.st_reg, r)), t[r]);
   }
@@ -524,7 +535,7 @@ k_fused_c64(f4* __restrict__ a, FusedArgs A, const FOp* __restrict__ ops,
       t[r] = f2{v.x, v.y};
       t[r + 1] = f2{v.z, v.w};
     }
-    run_ops<float, NREG, false, RUNS>(t, nullptr, lds, ops, A.nops, maps, base, nullptr);
+    run_ops<float, NREG, false, RUNS>(t, nullptr, lds, ops, A.nops, maps, base, nullptr, tile);
 #pragma unroll
     for (int r = 0; r < RA; r += 2)
       gstore<true>(a + ((base | ts | reg_global_off<NREG>(A.st_reg, r)) >> 1),
@@ -556,7 +567,7 @@ k_fused_adj_c128(d2* __restrict__ psi, d2* __restrict__ lam, FusedArgs A,
       t[r] = gload<true>(psi + i);
       l[r] = gload<true>(lam + i);
     }
-    run_ops<double, NREG, true>(t, l, lds, ops, A.nops, maps, base, acc);
+    run_ops<double, NREG, true>(t, l, lds, ops, A.nops, maps, base, acc, tile);
 #pragma unroll
     for (int r = 0; r < RA; ++r) {
       const uint64_t i = base | ts | reg_global_off<NREG>(A.st_reg, r);
@@ -592,7 +603,7 @@ k_fused_adj_c64(f4* __restrict__ psi, f4* __restrict__ lam, FusedArgs A,
       l[r] = f2{w.x, w.y};
       l[r + 1] = f2{w.z, w.w};
     }
-    run_ops<float, NREG, true>(t, l, lds, ops, A.nops, maps, base, acc);
+    run_ops<float, NREG, true>(t, l, lds, ops, A.nops, maps, base, acc, tile);
 #pragma unroll
     for (int r = 0; r < RA; r += 2) {
       const uint64_t u = (base | ts | reg_global_off<NREG>(A.st_reg, r)) >> 1;
@@ -641,13 +652,19 @@ static Status upload_plan(StateImpl* s, const Plan& plan, const FuseGeom& G, con
   for (const FMap& m : plan.maps) md.push_back(fmap_dev(m, G.nreg, s->dtype));
   // one zeroed record past the last op: the kernels prefetch op i + 1
   const size_t ob = (plan.ops.size() + 1) * sizeof(FOp), mb = md.size() * sizeof(FMapDev);
-  std::vector<char> blob(ob + mb, 0);
+  const size_t tb = plan.run_tab.size() * sizeof(double);  // phase-run tables, after the maps
+  std::vector<char> blob(ob + mb + tb, 0);
   memcpy(blob.data(), plan.ops.data(), plan.ops.size() * sizeof(FOp));
+  if (tb) memcpy(blob.data() + ob + mb, plan.run_tab.data(), tb);
   // diagonal ops with d0 = 1 (phases) leave target-bit-0 amplitudes alone
   FOp* fo = (FOp*)blob.data();
   for (size_t i = 0; i < plan.ops.size(); ++i)
     if ((fo[i].kind & 255) == kOpDiag && fo[i].m[0] == 1.0 && fo[i].m[1] == 0.0)
       fo[i].kind |= kDiagPhase;
+  // run tables: offset in run_tab -> byte offset from the maps
+  for (size_t i = 0; i < plan.ops.size(); ++i)
+    if ((fo[i].kind & 255) == kOpPhaseRun && fo[i].m[2] != 0.0)
+      fo[i].m[0] = (double)(mb + (size_t)fo[i].m[0] * sizeof(double));
   // U ops whose matrix is real (the adjoint kernels use the cheaper body;
   // the forward kernels ignore the flag)
   for (size_t i = 0; i < plan.ops.size(); ++i) {

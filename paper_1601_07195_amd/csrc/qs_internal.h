@@ -187,6 +187,10 @@ struct Plan {
   std::vector<int> order;  // gate indices in execution order
   std::vector<int> pass_of;  // pass of each gate (by gate index)
   std::vector<int> grad_rows;  // per fused pass slot: the gate's param (gradient row)
+  // Phase-run tables (re, im pairs): for a run's entries controlled by qubits
+  // outside the tile, the product of their phases by the tile index, split
+  // into a table over its low bits and one over its high bits.
+  std::vector<double> run_tab;
 };
 // Plan `gates` (applied in list order) for an n-qubit state of `dtype`.
 // allow_single: a pass with one gate may use the streaming kernels.

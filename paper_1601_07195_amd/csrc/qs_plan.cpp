@@ -139,6 +139,7 @@ void plan_gates(int n, int dtype, const std::vector<XGate>& gates, bool fuse, Pl
   out->maps.clear();
   out->order.clear();
   out->grad_rows.clear();
+  out->run_tab.clear();
   const int N = (int)gates.size();
   out->pass_of.assign(N, -1);
   const FuseGeom G = fuse_geom(dtype);
@@ -465,11 +466,51 @@ void plan_gates(int n, int dtype, const std::vector<XGate>& gates, bool fuse, Pl
             h.kind = kOpPhaseRun;
             h.tgt = blk[a].tgt;
             h.ctl = make_spec(kNoBit, 0);
-            h.aux = (int)(b - a + 1);
+            // entries controlled by a qubit outside the tile: their product
+            // depends only on the tile index, so it goes into two tables
+            // (low and high bits of the tile index) built here; the other
+            // entries stay explicit.  m[0]: the tables' offset in run_tab
+            // (made a byte offset at upload), m[1]: low-table bits, m[2]: 1
+            // when the run has tables.
+            std::vector<const FOp*> lane, outside;
+            for (size_t k = a; k <= b; ++k)
+              ((blk[k].ctl >> 8) == kOutside ? outside : lane).push_back(&blk[k]);
+            if (!outside.empty()) {
+              const int nb = n - G.T;  // tile-index bits
+              const int lb = (nb + 1) / 2, hb = nb - lb;
+              auto tile_bit = [&](int q) {  // tile-index bit of an outside qubit
+                int below = 0;
+                for (int t = 0; t < n && t < q; ++t) below += in_tile(t);
+                return q - below;
+              };
+              const size_t off = out->run_tab.size();
+              out->run_tab.resize(off + 2 * ((size_t)1 << lb) + 2 * ((size_t)1 << hb), 0.0);
+              double* tlo = out->run_tab.data() + off;
+              double* thi = tlo + 2 * ((size_t)1 << lb);
+              for (size_t x = 0; x < ((size_t)1 << lb); ++x) { tlo[2 * x] = 1.0; }
+              for (size_t x = 0; x < ((size_t)1 << hb); ++x) { thi[2 * x] = 1.0; }
+              for (const FOp* e : outside) {
+                const int j = tile_bit(e->ctl & 255);
+                const bool low = j < lb;
+                double* t = low ? tlo : thi;
+                const int bit = low ? j : j - lb;
+                const size_t size = (size_t)1 << (low ? lb : hb);
+                for (size_t x = 0; x < size; ++x) {
+                  if (!((x >> bit) & 1)) continue;
+                  const double r = t[2 * x], i = t[2 * x + 1];
+                  t[2 * x] = r * e->m[6] - i * e->m[7];
+                  t[2 * x + 1] = r * e->m[7] + i * e->m[6];
+                }
+              }
+              h.m[0] = (double)off;
+              h.m[1] = (double)lb;
+              h.m[2] = 1.0;
+            }
+            h.aux = (int)lane.size();
             nops.push_back(h);
             nmeta.push_back(om);
-            for (size_t k = a; k <= b; ++k) {
-              FOp e = blk[k];
+            for (const FOp* le : lane) {
+              FOp e = *le;
               e.kind = kOpPhaseEntry;
               nops.push_back(e);
               nmeta.push_back(om);
