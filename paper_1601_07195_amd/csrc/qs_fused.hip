@@ -355,9 +355,11 @@ __device__ __forceinline__ void run_ops(typename LdsAmp<R>::T* a, typename LdsAm
       // controlled outside the tile come as one product from the run's
       // tables; then the target-bit-1 amplitudes (target on a register bit,
       // a thread bit or outside the tile) are scaled once
-      // Entries are read four at a time (their scalar loads in flight
-      // together) into two product chains, even and odd entries, which are
-      // joined at the end.
+      // Two or more entries with no control or a thread-bit control come as
+      // one value per thread from a third table; a single such entry is read
+      // explicitly.  Explicit entries are read four at a time (their scalar
+      // loads in flight together) into two product chains, even and odd
+      // entries, which are joined at the end.
       auto factor = [&](int ec, double m6, double m7, R& fr, R& fi) {
         const int ew = ec >> 8, eb = ec & 255;
         const bool eon = ew == kNoBit || (ew == kInThread ? (bool)((threadIdx.x >> eb) & 1)
@@ -371,6 +373,13 @@ __device__ __forceinline__ void run_ops(typename LdsAmp<R>::T* a, typename LdsAm
         pr_ = t;
       };
       R pr = (R)1, pi = (R)0, qr = (R)1, qi = (R)0;
+      if (op->m[4] != 0.0) {
+        // entries with no control or a thread-bit control, folded into one
+        // product per thread
+        const double* tl = (const double*)((const char*)maps + (size_t)op->m[3]);
+        pr = (R)tl[2 * threadIdx.x];
+        pi = (R)tl[2 * threadIdx.x + 1];
+      }
       int e = 1;
       for (; e + 3 <= aux; e += 4) {
         int ec[4];
@@ -662,9 +671,11 @@ static Status upload_plan(StateImpl* s, const Plan& plan, const FuseGeom& G, con
     if ((fo[i].kind & 255) == kOpDiag && fo[i].m[0] == 1.0 && fo[i].m[1] == 0.0)
       fo[i].kind |= kDiagPhase;
   // run tables: offset in run_tab -> byte offset from the maps
-  for (size_t i = 0; i < plan.ops.size(); ++i)
-    if ((fo[i].kind & 255) == kOpPhaseRun && fo[i].m[2] != 0.0)
-      fo[i].m[0] = (double)(mb + (size_t)fo[i].m[0] * sizeof(double));
+  for (size_t i = 0; i < plan.ops.size(); ++i) {
+    if ((fo[i].kind & 255) != kOpPhaseRun) continue;
+    if (fo[i].m[2] != 0.0) fo[i].m[0] = (double)(mb + (size_t)fo[i].m[0] * sizeof(double));
+    if (fo[i].m[4] != 0.0) fo[i].m[3] = (double)(mb + (size_t)fo[i].m[3] * sizeof(double));
+  }
   // U ops whose matrix is real (the adjoint kernels use the cheaper body;
   // the forward kernels ignore the flag)
   for (size_t i = 0; i < plan.ops.size(); ++i) {

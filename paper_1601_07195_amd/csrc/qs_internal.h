@@ -150,11 +150,15 @@ struct FMap {
 enum SpecWhere { kInReg = 0, kInThread = 1, kOutside = 2, kNoBit = 3 };
 inline int32_t make_spec(int where, int index) { return (where << 8) | index; }
 
-// kOpPhaseRun: `aux` consecutive phase entries follow (kOpPhaseEntry, each a
-// diagonal op with d0 = 1, its control spec in `ctl` and no register
-// control); all share the run's target `tgt`, a register bit.  The kernel
-// multiplies the entries' d1 into one per-lane factor and scales the
-// target-bit-1 amplitudes once.
+// kOpPhaseRun: phase ops (diagonal, d0 = 1) on one target `tgt` (a register
+// bit, a thread bit or outside the tile) whose controls are not register
+// bits.  The kernel multiplies their d1 into one per-lane factor and scales
+// the target-bit-1 amplitudes once.  Entries controlled outside the tile
+// come from two tables indexed by the tile index (m[0]: byte offset from the
+// maps, m[1]: low-table bits, m[2]: present); two or more entries with no
+// control or a thread-bit control come from one table indexed by the thread
+// (m[3]: byte offset, m[4]: present); otherwise `aux` explicit entries follow
+// (kOpPhaseEntry, the control spec in `ctl`).
 enum FOpKind { kOpRemap = 0, kOpU = 1, kOpDiag = 2, kOpPhaseRun = 3, kOpPhaseEntry = 4 };
 // FOp::kind bits 8..15: the Pauli generator of a gradient op; bit 16 on a
 // diagonal op: d0 = 1 (a phase), set when the plan is uploaded.

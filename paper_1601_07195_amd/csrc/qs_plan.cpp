@@ -506,6 +506,30 @@ void plan_gates(int n, int dtype, const std::vector<XGate>& gates, bool fuse, Pl
               h.m[1] = (double)lb;
               h.m[2] = 1.0;
             }
+            // two or more entries with no control or a thread-bit control:
+            // their product by the thread index goes into one more table of
+            // one value per thread (m[3]: its offset in run_tab, made a byte
+            // offset at upload; m[4]: 1 when present), and no entries follow
+            if (lane.size() >= 2) {
+              constexpr size_t nt = (size_t)1 << kFuseThreadBits;
+              const size_t off = out->run_tab.size();
+              out->run_tab.resize(off + 2 * nt, 0.0);
+              double* t = out->run_tab.data() + off;
+              for (size_t x = 0; x < nt; ++x) t[2 * x] = 1.0;
+              for (const FOp* e : lane) {
+                const bool thr = (e->ctl >> 8) == kInThread;
+                const int bit = e->ctl & 255;
+                for (size_t x = 0; x < nt; ++x) {
+                  if (thr && !((x >> bit) & 1)) continue;
+                  const double r = t[2 * x], i = t[2 * x + 1];
+                  t[2 * x] = r * e->m[6] - i * e->m[7];
+                  t[2 * x + 1] = r * e->m[7] + i * e->m[6];
+                }
+              }
+              h.m[3] = (double)off;
+              h.m[4] = 1.0;
+              lane.clear();
+            }
             h.aux = (int)lane.size();
             nops.push_back(h);
             nmeta.push_back(om);
