@@ -67,6 +67,37 @@ def test_fused_diagonal_heavy(Q, name, n):
     assert np.abs(st.numpy() - ref).max() <= bound(name, 400)
 
 
+def phase_blocks(n, nblocks, rng):
+    """Blocks of consecutive phase gates diag(1, e^{i phi}) that share a
+    target: uncontrolled, or controlled by random qubits (in registers, on
+    thread bits or outside the tile, depending on the pass's map), with a
+    Haar-random gate between blocks.  Block sizes 1-12 give runs with no,
+    one and several per-lane entries and with tile-index entries."""
+    ops = []
+    for _ in range(nblocks):
+        t = int(rng.integers(n))
+        for _ in range(int(rng.integers(1, 13))):
+            ph = np.diag([1.0, np.exp(2j * np.pi * rng.random())])
+            if rng.random() < 0.25:
+                ops.append(C.op_u(t, ph))
+            else:
+                c = int(rng.choice([q for q in range(n) if q != t]))
+                ops.append(C.op_cu(c, t, ph))
+        ops.append(C.op_u(int(rng.integers(n)), C.haar_unitary(rng)))
+    return np.concatenate(ops)
+
+
+@pytest.mark.parametrize("name,n", [("c128", 13), ("c128", 17), ("c64", 15), ("c64", 18)])
+def test_fused_phase_blocks(Q, name, n):
+    rng = np.random.default_rng(750 + n)
+    ops = phase_blocks(n, 60, rng)
+    psi = random_state(n, rng)
+    st = to_gpu_state(Q, psi, dt(Q, name))
+    st.run(ops)
+    ref = O.run(ops, n, psi=rounded_input(psi, name == "c64"))
+    assert np.abs(st.numpy() - ref).max() <= bound(name, len(ops))
+
+
 def _bitrev(z, n):
     return int(format(z, "0%db" % n)[::-1], 2)
 
