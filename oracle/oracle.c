@@ -21,10 +21,9 @@
  * -fcx-limited-range (textbook complex product) and -ffp-contract=off.
  * Reductions accumulate in long double (x87 80-bit) in index order.
  *
- * OpenMP may split the independent iterations of a loop nest over threads
- * (Sec. 4.2 "Threading": the nest level with more iterations is the one
- * parallelised).  Every amplitude is still computed by exactly the formula
- * below, so the thread count never changes a result.
+ * OpenMP may split the independent iterations of a loop over threads.
+ * Every amplitude is still computed by exactly the formula below, so the
+ * thread count never changes a result.
  */
 #include <complex.h>
 #include <math.h>
@@ -56,63 +55,49 @@ void oracle_init_basis(cplx* a, int n, uint64_t idx) {
 }
 
 /*
- * Single-qubit gate on qubit k, Eq. (2), with the loop nest of Fig. 2: the
- * outer loop walks groups of 2^(k+1) amplitudes, the inner loop walks the
- * 2^k pairs (i, i + 2^k) inside a group.
+ * Index of the p-th pair's first member for target k: p with a 0 bit
+ * inserted at position k.  Its partner differs only in bit k.
+ */
+static int64_t pair_low(int64_t p, int k) {
+  const int64_t below = p & (((int64_t)1 << k) - 1);
+  return ((p - below) << 1) | below;
+}
+
+/*
+ * Single-qubit gate on qubit k, Eq. (2): every index pair (i0, i1) that
+ * differs only in bit k, with bit k of i0 equal to 0, takes the 2x2 matrix
+ * product (a[i0], a[i1]) <- Q (a[i0], a[i1]).  There are 2^(n-1) such pairs
+ * and each is updated independently of the others.
  */
 void oracle_apply_1q(cplx* a, int n, int k, const double* q) {
   const cplx q11 = entry(q, 0, 0), q12 = entry(q, 0, 1);
   const cplx q21 = entry(q, 1, 0), q22 = entry(q, 1, 1);
-  const int64_t N = (int64_t)1 << n, s = (int64_t)1 << k;
-  const int64_t outer = N / (2 * s);
-  if (outer >= s) {
+  const int64_t npairs = (int64_t)1 << (n - 1), bit = (int64_t)1 << k;
 #pragma omp parallel for num_threads(g_threads) if (g_threads > 1) schedule(static)
-    for (int64_t g = 0; g < N; g += 2 * s)
-      for (int64_t i = g; i < g + s; i++) {
-        const cplx x = a[i], y = a[i + s];
-        a[i] = q11 * x + q12 * y;
-        a[i + s] = q21 * x + q22 * y;
-      }
-  } else {
-    for (int64_t g = 0; g < N; g += 2 * s) {
-#pragma omp parallel for num_threads(g_threads) if (g_threads > 1) schedule(static)
-      for (int64_t i = g; i < g + s; i++) {
-        const cplx x = a[i], y = a[i + s];
-        a[i] = q11 * x + q12 * y;
-        a[i + s] = q21 * x + q22 * y;
-      }
-    }
+  for (int64_t p = 0; p < npairs; p++) {
+    const int64_t i0 = pair_low(p, k), i1 = i0 | bit;
+    const cplx x = a[i0], y = a[i1];
+    a[i0] = q11 * x + q12 * y;
+    a[i1] = q21 * x + q22 * y;
   }
 }
 
 /*
- * Controlled-Q with control c and target t, Eq. (3): the Fig. 2 loops over
- * the target's pairs, skipping every pair whose control bit is 0 (Sec. 3.1).
+ * Controlled-Q with control c and target t, Eq. (3): the pairs of Eq. (2)
+ * for target t, of which only those whose control bit is 1 are updated;
+ * the others keep their amplitudes.
  */
 void oracle_apply_cu(cplx* a, int n, int c, int t, const double* q) {
   const cplx q11 = entry(q, 0, 0), q12 = entry(q, 0, 1);
   const cplx q21 = entry(q, 1, 0), q22 = entry(q, 1, 1);
-  const int64_t N = (int64_t)1 << n, s = (int64_t)1 << t;
-  const int64_t outer = N / (2 * s);
-  if (outer >= s) {
+  const int64_t npairs = (int64_t)1 << (n - 1), bit = (int64_t)1 << t;
 #pragma omp parallel for num_threads(g_threads) if (g_threads > 1) schedule(static)
-    for (int64_t g = 0; g < N; g += 2 * s)
-      for (int64_t i = g; i < g + s; i++) {
-        if (((i >> c) & 1) == 0) continue;
-        const cplx x = a[i], y = a[i + s];
-        a[i] = q11 * x + q12 * y;
-        a[i + s] = q21 * x + q22 * y;
-      }
-  } else {
-    for (int64_t g = 0; g < N; g += 2 * s) {
-#pragma omp parallel for num_threads(g_threads) if (g_threads > 1) schedule(static)
-      for (int64_t i = g; i < g + s; i++) {
-        if (((i >> c) & 1) == 0) continue;
-        const cplx x = a[i], y = a[i + s];
-        a[i] = q11 * x + q12 * y;
-        a[i + s] = q21 * x + q22 * y;
-      }
-    }
+  for (int64_t p = 0; p < npairs; p++) {
+    const int64_t i0 = pair_low(p, t), i1 = i0 | bit;
+    if (((i0 >> c) & 1) == 0) continue;
+    const cplx x = a[i0], y = a[i1];
+    a[i0] = q11 * x + q12 * y;
+    a[i1] = q21 * x + q22 * y;
   }
 }
 
