@@ -99,9 +99,13 @@ const char* qs_last_error(void);
  *   stream   hipStream_t to queue work on (NULL = the null stream)
  *   out      receives the handle
  * The amplitudes are not touched (use qs_init_basis).  No GPU work is done
- * here; the device is the one current on the calling thread.
- * Errors: QS_EINVAL (NULL out/dev_ptr, bad dtype, misaligned), QS_ERANGE,
- * QS_ENOMEM (handle allocation), QS_ENODEV (no device current).
+ * here; the device is the one current on the calling thread, and dev_ptr
+ * must be device memory of that device (checked with the runtime's pointer
+ * attributes, so a host pointer is refused here rather than faulting later).
+ * Errors: QS_EINVAL (NULL out/dev_ptr, bad dtype, misaligned, not device
+ * memory of the current device), QS_ERANGE (bytes, or the allocation behind
+ * dev_ptr, too small), QS_ENOMEM (handle allocation), QS_ENODEV (no device
+ * current, or the current device is not a gfx950).
  */
 int qs_create(int n, int dtype, void* dev_ptr, size_t bytes, void* stream,
               qs_state** out);
@@ -112,6 +116,19 @@ int qs_destroy(qs_state* s);
 
 /* Queue later work of this state on another hipStream_t. */
 int qs_set_stream(qs_state* s, void* stream);
+
+/*
+ * Cap the number of workgroups of this state's fused passes (qs_run's
+ * cache-blocked passes, Sec. 4.4, and the reverse sweep of qs_grad_adjoint).
+ * 0, the default, lets the library choose (one workgroup per tile up to a
+ * launch limit).  A positive cap below the number of tiles makes every
+ * workgroup process several tiles in turn (a persistent grid), e.g. to leave
+ * compute units to concurrent work.  States are unaffected bit for bit;
+ * gradients change only in the rounding of their fixed-order sums, which
+ * depend on how tiles are shared among workgroups.
+ * Errors: QS_EINVAL (bad state, negative cap).
+ */
+int qs_set_grid_limit(qs_state* s, int max_workgroups);
 
 /* State = computational basis state |index> (index < 2^n); |0...0> for 0. */
 int qs_init_basis(qs_state* s, uint64_t index);
@@ -248,7 +265,8 @@ int qs_run_reordered(qs_state* s, int nlocal, const qs_op* ops, int nops, const 
  * per-qubit marginals of |alpha_i|^2):
  *   p1     host, n doubles or NULL: p1[k] = sum over i with bit k set of |alpha_i|^2
  *   norm2  host, 1 double or NULL: sum of all |alpha_i|^2
- *   full   dev, 2^n doubles or NULL: full[i] = |alpha_i|^2
+ *   full   dev, 2^n doubles or NULL: full[i] = |alpha_i|^2; device memory
+ *          of the state's GPU (QS_EINVAL otherwise)
  *   full_bytes  size of `full` (QS_ERANGE if smaller than 2^n doubles)
  * Sums are double, accumulated in a fixed order (bitwise reproducible run to
  * run).  Synchronises the stream when p1 or norm2 is given.
@@ -391,9 +409,11 @@ int qs_batch_destroy(qs_batch* b);
 /*
  * STREAM copy, dst[i] = src[i]: the sustainable-bandwidth probe that the
  * paper's lower bounds are stated against (Sec. 5.2, B_mem "measured by
- * STREAM Copy").  src, dst: device, 16-byte aligned, non-overlapping;
- * bytes: a multiple of 16.  Asynchronous on `stream`.
- * Errors: QS_EINVAL (NULL, misaligned, bytes % 16 != 0).
+ * STREAM Copy").  src, dst: device memory of the current device, 16-byte
+ * aligned, non-overlapping; bytes: a multiple of 16.  Asynchronous on
+ * `stream`.
+ * Errors: QS_EINVAL (NULL, misaligned, bytes % 16 != 0, not device memory),
+ * QS_ERANGE (an allocation smaller than bytes), QS_ENODEV.
  */
 int qs_stream_copy(const void* src, void* dst, size_t bytes, void* stream);
 

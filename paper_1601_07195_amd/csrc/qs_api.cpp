@@ -201,6 +201,47 @@ const char* qs_strerror(int code) {
 
 const char* qs_last_error(void) { return g_last_error.c_str(); }
 
+// The device must be a gfx950 (the only target the kernels are built for).
+static int check_device(int dev, const char* who) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(QS_ENODEV, std::string(who) + ": cannot query device " + std::to_string(dev));
+  }
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(QS_ENODEV, std::string(who) + ": device " + std::to_string(dev) + " is " +
+                               prop.gcnArchName + ", not gfx950");
+  return QS_OK;
+}
+
+// `ptr` must be device (or managed) memory of device `dev` with at least
+// `need` bytes from ptr to the end of its allocation.  A host pointer would
+// otherwise pass validation and fault on the first kernel.
+static int check_device_buffer(const void* ptr, size_t need, int dev, const std::string& what) {
+  hipPointerAttribute_t at;
+  memset(&at, 0, sizeof(at));
+  if (hipPointerGetAttributes(&at, ptr) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(QS_EINVAL, what + " is not device memory");
+  }
+  if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged)
+    return fail(QS_EINVAL, what + " is not device memory");
+  if (at.device != dev)
+    return fail(QS_EINVAL, what + " belongs to device " + std::to_string(at.device) +
+                               ", not the current device " + std::to_string(dev));
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)ptr) == hipSuccess && base && size) {
+    const size_t avail = size - (size_t)((const char*)ptr - (const char*)base);
+    if (avail < need)
+      return fail(QS_ERANGE, what + ": the allocation holds " + std::to_string(avail) +
+                                 " bytes from the pointer, fewer than " + std::to_string(need));
+  } else {
+    (void)hipGetLastError();
+  }
+  return QS_OK;
+}
+
 int qs_create(int n, int dtype, void* dev_ptr, size_t bytes, void* stream, qs_state** out) {
   if (!out) return fail(QS_EINVAL, "qs_create: out is NULL");
   *out = nullptr;
@@ -218,6 +259,12 @@ int qs_create(int n, int dtype, void* dev_ptr, size_t bytes, void* stream, qs_st
   if (hipGetDevice(&dev) != hipSuccess) {
     (void)hipGetLastError();
     return fail(QS_ENODEV, "qs_create: no HIP device");
+  }
+  {
+    int rc = check_device(dev, "qs_create");
+    if (rc) return rc;
+    rc = check_device_buffer(dev_ptr, need, dev, "qs_create: dev_ptr");
+    if (rc) return rc;
   }
   qs_state* s = new (std::nothrow) qs_state();
   if (!s) return fail(QS_ENOMEM, "qs_create: handle allocation failed");
@@ -256,6 +303,13 @@ int qs_set_stream(qs_state* s, void* stream) {
   Status st = qs::hip_status(hipStreamSynchronize(s->impl.stream), "qs_set_stream sync");
   if (!st.good()) return done(st);
   s->impl.stream = (hipStream_t)stream;
+  return QS_OK;
+}
+
+int qs_set_grid_limit(qs_state* s, int max_workgroups) {
+  if (!valid_state(s)) return fail(QS_EINVAL, "qs_set_grid_limit: bad state");
+  if (max_workgroups < 0) return fail(QS_EINVAL, "qs_set_grid_limit: negative limit");
+  s->impl.grid_limit = max_workgroups;
   return QS_OK;
 }
 
@@ -332,6 +386,9 @@ int qs_probabilities(qs_state* s, double* p1, double* norm2, void* full, size_t 
     if (((uintptr_t)full) & 7) return fail(QS_EINVAL, "qs_probabilities: full not 8-byte aligned");
     if (full_bytes < (((size_t)1) << s->impl.n) * sizeof(double))
       return fail(QS_ERANGE, "qs_probabilities: full buffer too small");
+    int rc = check_device_buffer(full, (((size_t)1) << s->impl.n) * sizeof(double), s->impl.device,
+                                 "qs_probabilities: full");
+    if (rc) return rc;
   }
   if (!p1 && !norm2 && !full) return QS_OK;
   return done(qs::launch_probabilities(&s->impl, p1, norm2, (double*)full));
@@ -518,6 +575,17 @@ int qs_stream_copy(const void* src, void* dst, size_t bytes, void* stream) {
     return fail(QS_EINVAL, "qs_stream_copy: pointers and size must be multiples of 16");
   const uintptr_t a = (uintptr_t)src, b = (uintptr_t)dst;
   if (a < b + bytes && b < a + bytes) return fail(QS_EINVAL, "qs_stream_copy: buffers overlap");
+  if (bytes) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(QS_ENODEV, "qs_stream_copy: no HIP device");
+    }
+    int rc = check_device_buffer(src, bytes, dev, "qs_stream_copy: src");
+    if (rc) return rc;
+    rc = check_device_buffer(dst, bytes, dev, "qs_stream_copy: dst");
+    if (rc) return rc;
+  }
   return done(qs::launch_stream_copy(src, dst, bytes, (hipStream_t)stream));
 }
 

@@ -721,7 +721,9 @@ Status run_gates(StateImpl* s, const std::vector<XGate>& gates, int flags) {
       st = launch_apply_cu(s, gates[p.gate].control, gates[p.gate].target, gates[p.gate].m);
     } else {
       const FusedArgs A = pass_args(s, plan, p, G);
-      const unsigned grid = (unsigned)std::min<uint64_t>(A.ntiles, (1ull << 31) / kFuseBlock);
+      uint64_t cap = (1ull << 31) / kFuseBlock;
+      if (s->grid_limit > 0) cap = std::min<uint64_t>(cap, (uint64_t)s->grid_limit);
+      const unsigned grid = (unsigned)std::min<uint64_t>(A.ntiles, cap);
       bool runs = false;
       for (int i = p.op_first; i < p.op_first + p.nops; ++i) runs |= plan.ops[i].kind == kOpPhaseRun;
       if (s->dtype == QS_C128) {
@@ -777,9 +779,13 @@ Status run_adjoint_fused(StateImpl* s, StateImpl* lam, const std::vector<XGate>&
   // arithmetic and stores of different workgroups overlap); each pass's
   // partials [slot][tile] are summed right after it, so the buffer holds one
   // pass.  Larger states use a persistent grid and one buffer for all passes.
-  const bool oneshot = ntiles <= (1ull << 19);
-  const unsigned grid = oneshot ? (unsigned)ntiles
-                                : (unsigned)std::min<uint64_t>(ntiles, (uint64_t)device_cus(s) * kAdjWgPerCu);
+  // A grid limit below the tile count forces the persistent grid.
+  const uint64_t limit = s->grid_limit > 0 ? (uint64_t)s->grid_limit : ~0ull;
+  const bool oneshot = ntiles <= (1ull << 19) && limit >= ntiles;
+  const unsigned grid =
+      oneshot ? (unsigned)ntiles
+              : (unsigned)std::min<uint64_t>(std::min<uint64_t>(ntiles, limit),
+                                             (uint64_t)device_cus(s) * kAdjWgPerCu);
   const size_t prow = oneshot ? (size_t)kAdjMaxSlots : nslots;
   st = ensure_dev(s, s->red, (prow * grid + nslots + 2) * sizeof(double));
   if (!st.good()) return st;

@@ -45,6 +45,7 @@ struct StateImpl {
   hipStream_t stream = nullptr;
   int device = 0;
   int cus = 0;       // compute units of the device (0 = not queried yet)
+  int grid_limit = 0;  // cap on a fused pass's workgroups (0 = automatic)
   DevBuf red;        // reduction partials
   DevBuf scal;       // small device results (energy)
   DevBuf table;      // uploaded tables

@@ -38,7 +38,7 @@ EXPORTED = ("qs_version", "qs_strerror", "qs_last_error", "qs_create", "qs_destr
             "qs_probabilities", "qs_expect_pauli", "qs_apply_pauli_sum", "qs_grad_adjoint",
             "qs_stream_copy", "qs_plan", "qs_batch_create", "qs_batch_run",
             "qs_batch_destroy", "qs_apply_kq", "qs_permute_qubits", "qs_plan_reorder",
-            "qs_run_reordered")
+            "qs_run_reordered", "qs_set_grid_limit")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1601_07195_amd.build`")
@@ -53,6 +53,7 @@ _L.qs_last_error.restype = ctypes.c_char_p
 _L.qs_create.argtypes = [_i, _i, _vp, _sz, _vp, ctypes.POINTER(_vp)]
 _L.qs_destroy.argtypes = [_vp]
 _L.qs_set_stream.argtypes = [_vp, _vp]
+_L.qs_set_grid_limit.argtypes = [_vp, _i]
 _L.qs_init_basis.argtypes = [_vp, _u64]
 _L.qs_apply_1q.argtypes = [_vp, _i, _dp]
 _L.qs_apply_cu.argtypes = [_vp, _i, _i, _dp]
@@ -191,6 +192,10 @@ def qs_destroy(h: int) -> None:
 
 def qs_set_stream(h: int, stream: int | None) -> None:
     _check(_L.qs_set_stream(h, stream), "qs_set_stream")
+
+
+def qs_set_grid_limit(h: int, max_workgroups: int) -> None:
+    _check(_L.qs_set_grid_limit(h, max_workgroups), "qs_set_grid_limit")
 
 
 def qs_init_basis(h: int, index: int = 0) -> None:
@@ -405,6 +410,10 @@ class State:
             self.close()
         except Exception:
             pass
+
+    def set_grid_limit(self, max_workgroups: int) -> "State":
+        qs_set_grid_limit(self.handle, max_workgroups)
+        return self
 
     def init_basis(self, index: int = 0) -> "State":
         qs_init_basis(self.handle, index)

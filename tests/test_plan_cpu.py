@@ -4,6 +4,8 @@ order on the CPU oracle gives the same state; every gate is applied once;
 and the pass counts behave as the cache-blocking argument predicts."""
 from __future__ import annotations
 
+import os
+
 import numpy as np
 import pytest
 
@@ -82,3 +84,53 @@ def test_plan_rejects_bad_ops(Q):
     ops[2]["target"] = 10
     with pytest.raises(Q.QSError):
         Q.qs_plan(10, Q.QS_C128, ops)
+
+
+def _table2_rows():
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "table2_bounds.txt")
+    rows = []
+    with open(path) as f:
+        for line in f:
+            if not line.strip() or line.startswith("#"):
+                continue
+            case, gate, cond, x, bw, sec = line.split()
+            rows.append((int(case), gate, cond, int(x), bw, float(sec)))
+    return rows
+
+
+def test_table2_printed_bounds_follow_from_the_byte_model(Q):
+    """Sec. 5.2, Table 2: every printed lower bound is 2^(m+x) bytes over the
+    bandwidth the case is bound by, at m = 29, B_mem = 40 GB/s, B_net = 5.5 GB/s
+    (printed to two decimals).  The byte counts are the library's own: a
+    gate pass on one device (qs_plan, cases 1, 3 and the control-1 shard of
+    case 4) and the pairwise exchanges of a state split by its top qubits
+    (qs_plan_reorder's traffic_pairwise, cases 2, 5 and 6, in shard sizes)."""
+    m = 29
+    bandwidth = {"mem": 40e9, "net": 5.5e9}
+    rows = _table2_rows()
+    assert [r[0] for r in rows] == [1, 2, 3, 4, 5, 6]
+    shard = (1 << m) * 16  # one shard of 2^m complex doubles = 2^(m+4) bytes
+    u = C.haar_unitary(np.random.default_rng(7))
+    p = 3  # 8 shards: the top three qubits are global
+    n = m + p
+    for case, gate, cond, x, bw, printed in rows:
+        t = 2.0 ** (m + x) / bandwidth[bw]
+        assert abs(t - printed) <= 0.005 + 1e-12, (case, t, printed)
+        if case == 1:      # 1q gate on a local target
+            ops = C.op_u(m - 1, u)
+        elif case == 3:    # controlled gate, both qubits local
+            ops = C.op_cu(3, m - 1, u)
+        elif case == 4:    # control global: on a control-1 shard every pair changes
+            ops = C.op_u(m - 1, u)
+        if case in (1, 3, 4):
+            info, _, _ = Q.qs_plan(m, Q.QS_C128, ops, flags=Q.QS_RUN_NO_FUSION)
+            assert info["hbm_bytes"] == 2 ** (m + x), (case, info["hbm_bytes"])
+            continue
+        if case == 2:      # 1q gate on a global target
+            ops = C.op_u(n - 1, u)
+        elif case == 5:    # global target, local control
+            ops = C.op_cu(3, n - 1, u)
+        else:              # both global
+            ops = C.op_cu(n - 2, n - 1, u)
+        info, *_ = Q.qs_plan_reorder(n, m, ops)
+        assert info["traffic_pairwise"] * shard == 2 ** (m + x), (case, info)
