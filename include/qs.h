@@ -275,6 +275,31 @@ int qs_probabilities(qs_state* s, double* p1, double* norm2, void* full,
                      size_t full_bytes);
 
 /*
+ * qs_probabilities for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and the same fixed-order sums, so the values equal those of
+ * qs_probabilities bit for bit, but nothing is allocated -- no hipMalloc,
+ * hipFree or pinned host buffer -- and nothing is copied to the host.
+ *   p1_dev     dev, n doubles or NULL: P(bit k = 1) as for qs_probabilities
+ *   norm2_dev  dev, 1 double or NULL: sum of all |alpha_i|^2
+ *   full, full_bytes  as for qs_probabilities
+ * Every output is device memory of the state's GPU (QS_EINVAL otherwise),
+ * 8-byte aligned.  Fully asynchronous on the state's stream; the results are
+ * valid once that stream reaches this point.
+ * Scratch: the partial sums live in one fixed device array of
+ * QS_NOALLOC_SCRATCH_BYTES per GPU, set up on the first call on that GPU and
+ * held until the process ends.  All calls on one GPU share it, so calls that
+ * can overlap in time on one GPU (different streams or host threads) race;
+ * calls queued on one stream are ordered and safe.  Every partial a call
+ * reads it writes first, so nothing needs clearing between calls.  A state
+ * whose partials would not fit gets QS_ERANGE (no state of n <= 34 does).
+ * Errors: QS_EINVAL, QS_ERANGE, QS_ENODEV, QS_EHIP.
+ */
+#define QS_NOALLOC_SCRATCH_BYTES ((size_t)2048 * 35 * 8 + 35 * 8) /* 573,720 bytes */
+int qs_probabilities_noalloc(qs_state* s, double* p1_dev, double* norm2_dev, void* full,
+                             size_t full_bytes);
+
+/*
  * Expectation value <psi|H|psi> of H = sum_j coeff[j] P_j, P_j the Pauli
  * string (x[j], z[j]) (not part of the paper).  The result is not divided
  * by the norm.  x, z, coeff: host arrays of nterms (nterms >= 0; every mask

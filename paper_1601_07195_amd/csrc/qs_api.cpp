@@ -394,6 +394,35 @@ int qs_probabilities(qs_state* s, double* p1, double* norm2, void* full, size_t 
   return done(qs::launch_probabilities(&s->impl, p1, norm2, (double*)full));
 }
 
+int qs_probabilities_noalloc(qs_state* s, double* p1_dev, double* norm2_dev, void* full,
+                             size_t full_bytes) {
+  if (!valid_state(s)) return fail(QS_EINVAL, "qs_probabilities_noalloc: bad state");
+  const int n = s->impl.n;
+  if (full) {
+    if (((uintptr_t)full) & 7) return fail(QS_EINVAL, "qs_probabilities_noalloc: full not 8-byte aligned");
+    if (full_bytes < (((size_t)1) << n) * sizeof(double))
+      return fail(QS_ERANGE, "qs_probabilities_noalloc: full buffer too small");
+    int rc = check_device_buffer(full, (((size_t)1) << n) * sizeof(double), s->impl.device,
+                                 "qs_probabilities_noalloc: full");
+    if (rc) return rc;
+  }
+  if (p1_dev) {
+    if (((uintptr_t)p1_dev) & 7) return fail(QS_EINVAL, "qs_probabilities_noalloc: p1 not 8-byte aligned");
+    int rc = check_device_buffer(p1_dev, (size_t)n * sizeof(double), s->impl.device,
+                                 "qs_probabilities_noalloc: p1");
+    if (rc) return rc;
+  }
+  if (norm2_dev) {
+    if (((uintptr_t)norm2_dev) & 7)
+      return fail(QS_EINVAL, "qs_probabilities_noalloc: norm2 not 8-byte aligned");
+    int rc = check_device_buffer(norm2_dev, sizeof(double), s->impl.device,
+                                 "qs_probabilities_noalloc: norm2");
+    if (rc) return rc;
+  }
+  if (!p1_dev && !norm2_dev && !full) return QS_OK;
+  return done(qs::launch_probabilities_noalloc(&s->impl, p1_dev, norm2_dev, (double*)full));
+}
+
 int qs_expect_pauli(qs_state* s, int nterms, const uint64_t* x, const uint64_t* z,
                     const double* coeff, double* out) {
   if (!valid_state(s)) return fail(QS_EINVAL, "qs_expect_pauli: bad state");

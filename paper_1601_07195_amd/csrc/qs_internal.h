@@ -75,6 +75,10 @@ Status launch_permute(StateImpl* s, const int32_t* perm);
 // ------------------------------------------------------------ reductions
 // Per-qubit P(bit = 1), total norm^2 and optionally the full |a_i|^2 vector.
 Status launch_probabilities(StateImpl* s, double* p1_host, double* norm2_host, double* full_dev);
+// The same sums with the partials in a static per-device array (no
+// allocation); p1_dev / norm2_dev are device outputs.  Asynchronous.
+Status launch_probabilities_noalloc(StateImpl* s, double* p1_dev, double* norm2_dev,
+                                    double* full_dev);
 
 // Pauli-sum terms grouped by x mask, in the device layout of the reduction
 // kernels (see qs_reduce.hip).

@@ -9,6 +9,8 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
+#include <string>
 
 #include "qs_device.h"
 #include "qs_internal.h"
@@ -285,17 +287,12 @@ static unsigned reduce_grid(uint64_t items, int per_block) {
   return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(g, kReduceGrid));
 }
 
-Status launch_probabilities(StateImpl* s, double* p1_host, double* norm2_host, double* full_dev) {
+// Queue the partial-sum pass over the state (partials at `part`, grid rows
+// of n + 1) and, when `fin` is given, the fixed-order column sums into
+// fin[0 .. n]: P(bit k = 1) for k < n, then the total.
+static Status queue_probabilities(StateImpl* s, double* part, double* fin, double* full_dev,
+                                  unsigned grid, uint64_t nchunks) {
   const int n = s->n;
-  const uint64_t N = 1ull << n;
-  const int cl = s->dtype == QS_C128 ? kProbChunkLog : kProbChunkLog + 1;  // log2 amplitudes per chunk
-  const uint64_t nchunks = (N + (1ull << cl) - 1) >> cl;
-  const unsigned grid = (unsigned)std::min<uint64_t>(nchunks, kReduceGrid);
-  const size_t ncols = (size_t)n + 1;
-  Status st = ensure_dev(s, s->red, (grid * ncols + ncols) * sizeof(double));
-  if (!st.good()) return st;
-  double* part = (double*)s->red.ptr;
-  double* fin = part + grid * ncols;
   if (s->dtype == QS_C128) {
     if (full_dev)
       hipLaunchKernelGGL((k_probabilities<d2, true>), dim3(grid), dim3(kBlock), 0, s->stream,
@@ -311,13 +308,35 @@ Status launch_probabilities(StateImpl* s, double* p1_host, double* norm2_host, d
       hipLaunchKernelGGL((k_probabilities_c64<false>), dim3(grid), dim3(kBlock), 0, s->stream,
                          (const f4*)s->ptr, n, nchunks, part, nullptr);
   }
-  st = last_launch("probabilities");
+  Status st = last_launch("probabilities");
+  if (!st.good() || !fin) return st;
+  hipLaunchKernelGGL(k_sum_columns, dim3(1), dim3(kBlock), 0, s->stream, part, (int)grid, n + 1,
+                     fin);
+  return last_launch("probabilities final");
+}
+
+// Launch shape of the probabilities pass: chunks of 2^12 (complex128) or
+// 2^13 (complex64) amplitudes, at most kReduceGrid workgroups.
+static void probabilities_shape(const StateImpl* s, unsigned* grid, uint64_t* nchunks) {
+  const uint64_t N = 1ull << s->n;
+  const int cl = s->dtype == QS_C128 ? kProbChunkLog : kProbChunkLog + 1;  // log2 amplitudes per chunk
+  *nchunks = (N + (1ull << cl) - 1) >> cl;
+  *grid = (unsigned)std::min<uint64_t>(*nchunks, kReduceGrid);
+}
+
+Status launch_probabilities(StateImpl* s, double* p1_host, double* norm2_host, double* full_dev) {
+  const int n = s->n;
+  unsigned grid;
+  uint64_t nchunks;
+  probabilities_shape(s, &grid, &nchunks);
+  const size_t ncols = (size_t)n + 1;
+  Status st = ensure_dev(s, s->red, (grid * ncols + ncols) * sizeof(double));
   if (!st.good()) return st;
-  if (!p1_host && !norm2_host) return Status::ok();
-  hipLaunchKernelGGL(k_sum_columns, dim3(1), dim3(kBlock), 0, s->stream, part, (int)grid,
-                     (int)ncols, fin);
-  st = last_launch("probabilities final");
-  if (!st.good()) return st;
+  double* part = (double*)s->red.ptr;
+  double* fin = part + grid * ncols;
+  const bool sums = p1_host || norm2_host;
+  st = queue_probabilities(s, part, sums ? fin : nullptr, full_dev, grid, nchunks);
+  if (!st.good() || !sums) return st;
   st = ensure_result_host(s, ncols * sizeof(double));
   if (!st.good()) return st;
   st = hip_status(hipMemcpyAsync(s->result_host, fin, ncols * sizeof(double),
@@ -329,6 +348,89 @@ Status launch_probabilities(StateImpl* s, double* p1_host, double* norm2_host, d
     for (int k = 0; k < n; ++k) p1_host[k] = s->result_host[k];
   if (norm2_host) *norm2_host = s->result_host[n];
   return Status::ok();
+}
+
+// ------------------------------------------------- allocation-free variant
+// The partial sums of qs_probabilities_noalloc live in this file-scope
+// device array: one copy per GPU, held until the process ends.  In host code
+// the name `scratch` is only a host-side stand-in; the device address of
+// each GPU's copy is looked up once per device (hipGetSymbolAddress, with
+// that device current) and only that address is passed to kernels.
+constexpr size_t kNoAllocScratchDoubles = (size_t)kReduceGrid * (kMaxQubits + 1) + (kMaxQubits + 1);
+static_assert(kNoAllocScratchDoubles * sizeof(double) == QS_NOALLOC_SCRATCH_BYTES,
+              "QS_NOALLOC_SCRATCH_BYTES must match the scratch array");
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_dev[kMaxDevices] = {};
+
+static Status scratch_address(int device, double** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices) {
+    Status st;
+    st.code = QS_ENODEV;
+    st.msg = "device index " + std::to_string(device) + " beyond the scratch table";
+    return st;
+  }
+  if (!g_scratch_dev[device]) {
+    int cur = -1;
+    Status st = hip_status(hipGetDevice(&cur), "scratch: hipGetDevice");
+    if (!st.good()) return st;
+    if (cur != device) {
+      st = hip_status(hipSetDevice(device), "scratch: hipSetDevice");
+      if (!st.good()) return st;
+    }
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    st = hip_status(e, "scratch: hipGetSymbolAddress");
+    if (!st.good()) return st;
+    if (!ptr) {
+      st.code = QS_EHIP;
+      st.msg = "scratch: hipGetSymbolAddress returned NULL";
+      return st;
+    }
+    g_scratch_dev[device] = (double*)ptr;
+  }
+  *out = g_scratch_dev[device];
+  return Status::ok();
+}
+
+// p1[k] = fin[k] (k < n), norm2 = fin[n]; either output may be absent.
+__global__ void k_copy_prob_results(const double* __restrict__ fin, int n, double* __restrict__ p1,
+                                    double* __restrict__ norm2) {
+  const int k = threadIdx.x;
+  if (p1 && k < n) p1[k] = fin[k];
+  if (norm2 && k == n) *norm2 = fin[n];
+}
+
+Status launch_probabilities_noalloc(StateImpl* s, double* p1_dev, double* norm2_dev,
+                                    double* full_dev) {
+  const int n = s->n;
+  unsigned grid;
+  uint64_t nchunks;
+  probabilities_shape(s, &grid, &nchunks);
+  const size_t ncols = (size_t)n + 1;
+  const size_t need = grid * ncols + ncols;
+  if (need > kNoAllocScratchDoubles) {
+    Status st;
+    st.code = QS_ERANGE;
+    st.msg = "probabilities need " + std::to_string(need * sizeof(double)) +
+             " bytes of scratch, more than the " + std::to_string(QS_NOALLOC_SCRATCH_BYTES) + " held";
+    return st;
+  }
+  double* base = nullptr;
+  Status st = scratch_address(s->device, &base);
+  if (!st.good()) return st;
+  double* part = base;
+  double* fin = part + grid * ncols;
+  const bool sums = p1_dev || norm2_dev;
+  st = queue_probabilities(s, part, sums ? fin : nullptr, full_dev, grid, nchunks);
+  if (!st.good() || !sums) return st;
+  hipLaunchKernelGGL(k_copy_prob_results, dim3(1), dim3(64), 0, s->stream, fin, n, p1_dev,
+                     norm2_dev);
+  return last_launch("probabilities results");
 }
 
 Status build_pauli_table(int n, int nterms, const uint64_t* x, const uint64_t* z,

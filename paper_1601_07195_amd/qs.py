@@ -28,6 +28,7 @@ QS_RUN_NO_FUSION = 1
 QS_ADJ_STATE_IS_FINAL = 1
 QS_BATCH_MAX_QUBITS = 24
 QS_KQ_MAX = 5
+QS_NOALLOC_SCRATCH_BYTES = 2048 * 35 * 8 + 35 * 8
 
 # Mirror of `struct qs_op` (80 bytes).
 QS_OP_DTYPE = np.dtype([("kind", "<i4"), ("target", "<i4"), ("control", "<i4"),
@@ -38,7 +39,7 @@ EXPORTED = ("qs_version", "qs_strerror", "qs_last_error", "qs_create", "qs_destr
             "qs_probabilities", "qs_expect_pauli", "qs_apply_pauli_sum", "qs_grad_adjoint",
             "qs_stream_copy", "qs_plan", "qs_batch_create", "qs_batch_run",
             "qs_batch_destroy", "qs_apply_kq", "qs_permute_qubits", "qs_plan_reorder",
-            "qs_run_reordered", "qs_set_grid_limit")
+            "qs_run_reordered", "qs_set_grid_limit", "qs_probabilities_noalloc")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1601_07195_amd.build`")
@@ -60,6 +61,7 @@ _L.qs_apply_cu.argtypes = [_vp, _i, _i, _dp]
 _L.qs_apply_kq.argtypes = [_vp, _i, _vp, _dp]
 _L.qs_run.argtypes = [_vp, _vp, _i, _dp, _i, _i]
 _L.qs_probabilities.argtypes = [_vp, _dp, _dp, _vp, _sz]
+_L.qs_probabilities_noalloc.argtypes = [_vp, _vp, _vp, _vp, _sz]
 _L.qs_expect_pauli.argtypes = [_vp, _i, _vp, _vp, _dp, _dp]
 _L.qs_apply_pauli_sum.argtypes = [_vp, _vp, _i, _vp, _vp, _dp]
 _L.qs_grad_adjoint.argtypes = [_vp, _vp, _i, _dp, _i, _i, _vp, _vp, _dp, _vp, _i, _dp, _dp]
@@ -240,6 +242,20 @@ def qs_probabilities(h: int, n: int, full_tensor: torch.Tensor | None = None, wa
         fptr, fbytes = full_tensor.data_ptr(), full_tensor.numel() * 8
     _check(_L.qs_probabilities(h, _ptr(p1), _ptr(nrm), fptr, fbytes), "qs_probabilities")
     return p1, float(nrm[0])
+
+
+def qs_probabilities_noalloc(h: int, p1: torch.Tensor | None, norm2: torch.Tensor | None,
+                             full: torch.Tensor | None = None) -> None:
+    """Allocation-free probabilities into float64 GPU tensors (asynchronous)."""
+    def dev(t):
+        if t is None:
+            return None
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("outputs must be contiguous float64 GPU tensors")
+        return t.data_ptr()
+    fb = 0 if full is None else full.numel() * 8
+    _check(_L.qs_probabilities_noalloc(h, dev(p1), dev(norm2), dev(full), fb),
+           "qs_probabilities_noalloc")
 
 
 def qs_expect_pauli(h: int, x, z, coeff) -> float:
