@@ -130,6 +130,55 @@ int qs_set_stream(qs_state* s, void* stream);
  */
 int qs_set_grid_limit(qs_state* s, int max_workgroups);
 
+/*
+ * How this state's fused passes (qs_run's cache-blocked passes, Sec. 4.4,
+ * and the reverse sweep of qs_grad_adjoint) execute:
+ *   QS_EXEC_INTERPRETED  one precompiled kernel per dtype decodes the
+ *                        pass's op list as it runs;
+ *   QS_EXEC_COMPILED     each pass gets its own straight-line kernel,
+ *                        generated from its op list and compiled at run time
+ *                        (hipRTC) the first time a pass of that shape runs,
+ *                        then cached for the process: the same circuit form
+ *                        with other matrices or angles runs without
+ *                        compiling again;
+ *   QS_EXEC_AUTO         (default) compiled for n >= 26, interpreted below;
+ *                        the environment variable QS_FUSED_EXEC set to
+ *                        "compiled" or "interpreted" overrides AUTO for every
+ *                        state.
+ * Both give the same amplitudes up to floating-point rounding (the order of
+ * operations inside a pass may differ).  A pass the generator does not take
+ * runs interpreted.  Compilation needs no GPU (see qs_precompile); its cost
+ * is reported by qs_jit_stats.
+ * Errors: QS_EINVAL (bad state or mode).
+ */
+#define QS_EXEC_AUTO 0
+#define QS_EXEC_INTERPRETED 1
+#define QS_EXEC_COMPILED 2
+int qs_set_fused_exec(qs_state* s, int mode);
+
+/*
+ * Compile, without running anything, the fused-pass kernels that qs_run
+ * (and, with QS_PRECOMPILE_ADJOINT, the reverse sweep of qs_grad_adjoint)
+ * would use for this gate list on an n-qubit state of `dtype`, so that a
+ * later call starts without compiling.  Host only; no GPU is needed.
+ * Arguments as for qs_plan.  *nkernels (may be NULL) receives the number of
+ * distinct pass kernels the list needs.
+ * Errors: QS_EINVAL (malformed list), QS_EHIP (compiler failure; the message
+ * holds the compiler's log).
+ */
+#define QS_PRECOMPILE_ADJOINT 1
+int qs_precompile(int n, int dtype, const qs_op* ops, int nops, const double* theta,
+                  int nparams, int flags, int32_t* nkernels);
+
+/* Counters of the compiled-pass cache of this process. */
+typedef struct qs_jit_stats {
+  int64_t kernels_compiled;  /* kernels compiled so far */
+  int64_t kernels_cached;    /* kernels held in the cache */
+  int64_t modules_loaded;    /* code objects loaded onto devices */
+  double compile_seconds;    /* host wall time spent compiling */
+} qs_jit_stats;
+int qs_get_jit_stats(qs_jit_stats* out);
+
 /* State = computational basis state |index> (index < 2^n); |0...0> for 0. */
 int qs_init_basis(qs_state* s, uint64_t index);
 

@@ -23,7 +23,8 @@ OBJDIR = os.path.join(HERE, "_build")
 ARCH = "gfx950"
 
 SOURCES = ["qs_api.cpp", "qs_plan.cpp", "qs_gates.hip", "qs_reduce.hip", "qs_fused.hip",
-           "qs_adjoint.hip", "qs_batch.hip", "qs_kq.hip", "qs_perm.hip", "qs_reorder.cpp"]
+           "qs_adjoint.hip", "qs_batch.hip", "qs_kq.hip", "qs_perm.hip", "qs_reorder.cpp",
+           "qs_jit.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{INCLUDE}", f"-I{CSRC}", "-Wall"]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -60,7 +61,7 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lhiprtc"]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -138,6 +138,16 @@ static Status reverse_sweep(StateImpl* s, StateImpl* lam, const std::vector<XGat
   return Status::ok();
 }
 
+void reverse_daggered(const std::vector<XGate>& gates, std::vector<XGate>* rev) {
+  rev->clear();
+  rev->reserve(gates.size());
+  for (int g = (int)gates.size() - 1; g >= 0; --g) {
+    XGate x = gates[g];
+    dagger(gates[g].m, x.m);
+    rev->push_back(x);
+  }
+}
+
 Status run_adjoint(StateImpl* s, StateImpl* lam, const std::vector<XGate>& gates, int nparams,
                    const PauliTable& h, int flags, double* energy, double* grad) {
   Status st;
@@ -162,12 +172,7 @@ Status run_adjoint(StateImpl* s, StateImpl* lam, const std::vector<XGate>& gates
   double* sums = nullptr;
   if (s->n >= fuse_geom(s->dtype).T) {
     std::vector<XGate> rev;
-    rev.reserve(gates.size());
-    for (int g = (int)gates.size() - 1; g >= 0; --g) {
-      XGate x = gates[g];
-      dagger(gates[g].m, x.m);
-      rev.push_back(x);
-    }
+    reverse_daggered(gates, &rev);
     st = run_adjoint_fused(s, &lam_on_s, rev, &rows, &sums);
     if (!st.good()) return st;
   } else {

@@ -313,6 +313,42 @@ int qs_set_grid_limit(qs_state* s, int max_workgroups) {
   return QS_OK;
 }
 
+int qs_set_fused_exec(qs_state* s, int mode) {
+  if (!valid_state(s)) return fail(QS_EINVAL, "qs_set_fused_exec: bad state");
+  if (mode != QS_EXEC_AUTO && mode != QS_EXEC_INTERPRETED && mode != QS_EXEC_COMPILED)
+    return fail(QS_EINVAL, "qs_set_fused_exec: unknown mode");
+  s->impl.exec = mode;
+  return QS_OK;
+}
+
+int qs_precompile(int n, int dtype, const qs_op* ops, int nops, const double* theta, int nparams,
+                  int flags, int32_t* nkernels) {
+  if (nkernels) *nkernels = 0;
+  if (dtype != QS_C64 && dtype != QS_C128) return fail(QS_EINVAL, "qs_precompile: bad dtype");
+  if (n < 1 || n > max_qubits(dtype)) return fail(QS_ERANGE, "qs_precompile: n out of range");
+  if (nops < 0 || (nops > 0 && !ops)) return fail(QS_EINVAL, "qs_precompile: bad op list");
+  if (nparams < 0) return fail(QS_EINVAL, "qs_precompile: nparams < 0");
+  if (flags & ~QS_PRECOMPILE_ADJOINT) return fail(QS_EINVAL, "qs_precompile: unknown flags");
+  std::vector<qs::XGate> gates;
+  Status st = qs::normalize_ops(n, ops, nops, theta, nparams, &gates);
+  if (!st.good()) return done(st);
+  int nk = 0;
+  st = qs::precompile_passes(n, dtype, gates, (flags & QS_PRECOMPILE_ADJOINT) != 0, &nk);
+  if (!st.good()) return done(st);
+  if (nkernels) *nkernels = nk;
+  return QS_OK;
+}
+
+int qs_get_jit_stats(qs_jit_stats* out) {
+  if (!out) return fail(QS_EINVAL, "qs_get_jit_stats: out is NULL");
+  const qs::JitStats j = qs::jit_stats();
+  out->kernels_compiled = j.kernels;
+  out->kernels_cached = j.cached;
+  out->modules_loaded = j.modules_loaded;
+  out->compile_seconds = j.compile_seconds;
+  return QS_OK;
+}
+
 int qs_init_basis(qs_state* s, uint64_t index) {
   if (!valid_state(s)) return fail(QS_EINVAL, "qs_init_basis: bad state");
   if (index >= (1ull << s->impl.n)) return fail(QS_EINVAL, "qs_init_basis: index >= 2^n");

@@ -9,6 +9,7 @@
 // bits become register bits; diagonal gates scale each amplitude by the
 // entry its target bit selects, wherever that bit lives (register, thread
 // index, or outside the tile).
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -705,15 +706,68 @@ static FusedArgs pass_args(const StateImpl* s, const Plan& plan, const Pass& p, 
   return A;
 }
 
+static int device_cus(StateImpl* s);
+
+bool use_compiled_passes(const StateImpl* s) {
+  if (s->exec == QS_EXEC_COMPILED) return true;
+  if (s->exec == QS_EXEC_INTERPRETED) return false;
+  const char* e = getenv("QS_FUSED_EXEC");
+  if (e && !strcmp(e, "compiled")) return true;
+  if (e && !strcmp(e, "interpreted")) return false;
+  return s->n >= kJitAutoMinQubits;
+}
+
+// Launch a compiled pass kernel; args: the kernel's arguments in order.
+static Status launch_compiled(StateImpl* s, const JitPass& jp, unsigned grid, void** args) {
+  hipFunction_t f = nullptr;
+  Status st = jit_function(jp, s->device, &f);
+  if (!st.good()) return st;
+  return hip_status(hipModuleLaunchKernel(f, grid, 1, 1, kFuseBlock, 1, 1, 0, s->stream, args, nullptr),
+                    "compiled fused pass");
+}
+
+Status precompile_passes(int n, int dtype, const std::vector<XGate>& gates, bool adjoint,
+                         int* nkernels) {
+  std::vector<JitPass> jp;
+  Plan plan;
+  plan_gates(n, dtype, gates, true, &plan);
+  Status st = jit_prepare(plan, n, dtype, false, &jp);
+  if (!st.good()) return st;
+  std::vector<int> used;
+  auto count = [&](const std::vector<JitPass>& v) {
+    for (const JitPass& j : v)
+      if (j.entry >= 0 && std::find(used.begin(), used.end(), j.entry) == used.end())
+        used.push_back(j.entry);
+  };
+  count(jp);
+  if (adjoint && n >= fuse_geom(dtype).T) {
+    std::vector<XGate> rev;
+    reverse_daggered(gates, &rev);
+    Plan ap;
+    plan_gates(n, dtype, rev, true, &ap, /*allow_single=*/false, kAdjMaxSlots, /*grad=*/true);
+    st = jit_prepare(ap, n, dtype, true, &jp);
+    if (!st.good()) return st;
+    count(jp);
+  }
+  *nkernels = (int)used.size();
+  return Status::ok();
+}
+
 Status run_gates(StateImpl* s, const std::vector<XGate>& gates, int flags) {
   Plan plan;
   plan_gates(s->n, s->dtype, gates, !(flags & QS_RUN_NO_FUSION), &plan);
   const FuseGeom G = fuse_geom(s->dtype);
+  std::vector<JitPass> jp;
+  if (use_compiled_passes(s)) {
+    Status st = jit_prepare(plan, s->n, s->dtype, false, &jp);
+    if (!st.good()) return st;
+  }
   const FOp* dops;
   const FMapDev* dmaps;
   Status up = upload_plan(s, plan, G, &dops, &dmaps);
   if (!up.good()) return up;
-  for (const Pass& p : plan.passes) {
+  for (size_t pi = 0; pi < plan.passes.size(); ++pi) {
+    const Pass& p = plan.passes[pi];
     Status st;
     if (p.kind == kPass1q) {
       st = launch_apply_1q(s, gates[p.gate].target, gates[p.gate].m);
@@ -726,6 +780,19 @@ Status run_gates(StateImpl* s, const std::vector<XGate>& gates, int flags) {
       const unsigned grid = (unsigned)std::min<uint64_t>(A.ntiles, cap);
       bool runs = false;
       for (int i = p.op_first; i < p.op_first + p.nops; ++i) runs |= plan.ops[i].kind == kOpPhaseRun;
+      if (!jp.empty() && jp[pi].entry >= 0) {
+        unsigned g = grid;
+        if (jp[pi].persistent)
+          g = (unsigned)std::min<uint64_t>(g, (uint64_t)device_cus(s) * jit_pipe_wg_per_cu());
+        void* a = s->ptr;
+        const FOp* o = dops + p.op_first;
+        const void* mp = dmaps;
+        unsigned long long nt = A.ntiles;
+        void* args[] = {&a, &o, &mp, &nt};
+        st = launch_compiled(s, jp[pi], g, args);
+        if (!st.good()) return st;
+        continue;
+      }
       if (s->dtype == QS_C128) {
         if (runs)
           hipLaunchKernelGGL((k_fused_c128<3, true>), dim3(grid), dim3(kFuseBlock), 0, s->stream,
@@ -769,9 +836,15 @@ Status run_adjoint_fused(StateImpl* s, StateImpl* lam, const std::vector<XGate>&
   Plan plan;
   plan_gates(s->n, s->dtype, rev, true, &plan, /*allow_single=*/false, kAdjMaxSlots, /*grad=*/true);
   const FuseGeom G = fuse_geom(s->dtype);
+  std::vector<JitPass> jp;
+  Status st;
+  if (use_compiled_passes(s)) {
+    st = jit_prepare(plan, s->n, s->dtype, true, &jp);
+    if (!st.good()) return st;
+  }
   const FOp* dops;
   const FMapDev* dmaps;
-  Status st = upload_plan(s, plan, G, &dops, &dmaps);
+  st = upload_plan(s, plan, G, &dops, &dmaps);
   if (!st.good()) return st;
   const uint64_t ntiles = 1ull << (s->n - G.T);
   const size_t nslots = plan.grad_rows.size();
@@ -791,16 +864,27 @@ Status run_adjoint_fused(StateImpl* s, StateImpl* lam, const std::vector<XGate>&
   if (!st.good()) return st;
   double* part = (double*)s->red.ptr;
   double* sums = part + prow * grid;
-  for (const Pass& p : plan.passes) {
+  for (size_t pi = 0; pi < plan.passes.size(); ++pi) {
+    const Pass& p = plan.passes[pi];
     const FusedArgs A = pass_args(s, plan, p, G);
     double* pp = oneshot ? part : part + (size_t)p.grad_first * grid;
-    if (s->dtype == QS_C128)
-      hipLaunchKernelGGL((k_fused_adj_c128<3>), dim3(grid), dim3(kFuseBlock), 0, s->stream,
-                         (d2*)s->ptr, (d2*)lam->ptr, A, dops + p.op_first, dmaps, pp);
-    else
-      hipLaunchKernelGGL((k_fused_adj_c64<4>), dim3(grid), dim3(kFuseBlock), 0, s->stream,
-                         (f4*)s->ptr, (f4*)lam->ptr, A, dops + p.op_first, dmaps, pp);
-    st = last_launch("fused adjoint pass");
+    if (!jp.empty() && jp[pi].entry >= 0) {
+      void* a = s->ptr;
+      void* l = lam->ptr;
+      const FOp* o = dops + p.op_first;
+      const void* mp = dmaps;
+      unsigned long long nt = A.ntiles;
+      void* args[] = {&a, &l, &o, &mp, &pp, &nt};
+      st = launch_compiled(s, jp[pi], grid, args);
+    } else {
+      if (s->dtype == QS_C128)
+        hipLaunchKernelGGL((k_fused_adj_c128<3>), dim3(grid), dim3(kFuseBlock), 0, s->stream,
+                           (d2*)s->ptr, (d2*)lam->ptr, A, dops + p.op_first, dmaps, pp);
+      else
+        hipLaunchKernelGGL((k_fused_adj_c64<4>), dim3(grid), dim3(kFuseBlock), 0, s->stream,
+                           (f4*)s->ptr, (f4*)lam->ptr, A, dops + p.op_first, dmaps, pp);
+      st = last_launch("fused adjoint pass");
+    }
     if (!st.good()) return st;
     if (oneshot && p.ngrad > 0) {
       st = launch_sum_rows(s, part, p.ngrad, (int)grid, sums + p.grad_first);

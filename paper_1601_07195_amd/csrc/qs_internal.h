@@ -46,6 +46,7 @@ struct StateImpl {
   int device = 0;
   int cus = 0;       // compute units of the device (0 = not queried yet)
   int grid_limit = 0;  // cap on a fused pass's workgroups (0 = automatic)
+  int exec = QS_EXEC_AUTO;  // fused passes: compiled per shape or interpreted
   DevBuf red;        // reduction partials
   DevBuf scal;       // small device results (energy)
   DevBuf table;      // uploaded tables
@@ -222,6 +223,41 @@ Status run_adjoint_fused(StateImpl* s, StateImpl* lam, const std::vector<XGate>&
 Status launch_sum_rows(StateImpl* s, const double* part, int nrows, int ncols, double* out);
 constexpr int kAdjMaxSlots = 64;  // gradient rows per fused adjoint pass
 bool gate_is_diagonal(const XGate& g);
+
+// ------------------------------------------- fused passes compiled per shape
+// A pass's kernel is generated from its plan (straight-line code, every
+// structural field fixed) and compiled through hipRTC; kernels are cached by
+// their text.  entry < 0: the pass runs on the interpreter kernels.
+struct JitPass {
+  int entry = -1;
+  bool persistent = false;  // a software-pipelined loop over tiles: launch a resident grid
+};
+int jit_pipe_wg_per_cu();
+struct JitStats {
+  long long kernels = 0;         // kernels compiled by this process
+  long long cached = 0;          // kernels held in the cache
+  long long modules_loaded = 0;  // code objects loaded on a device
+  double compile_seconds = 0.0;  // wall time spent compiling
+};
+// Kernel text of one fused pass (after the kernel's name); empty when the
+// generator does not take the pass.
+std::string jit_pass_text(const Plan& plan, const Pass& p, int n, int dtype, bool adjoint);
+// Compile (or find in the cache) the kernels of every fused pass of `plan`.
+Status jit_prepare(const Plan& plan, int n, int dtype, bool adjoint, std::vector<JitPass>* out);
+// The pass's kernel on `device` (its module is loaded on first use).
+Status jit_function(const JitPass& jp, int device, hipFunction_t* fn);
+JitStats jit_stats();
+// Whether the state's fused passes run compiled kernels (QS_EXEC_AUTO: from
+// kJitAutoMinQubits qubits up, or as the QS_FUSED_EXEC environment variable
+// says: "compiled" or "interpreted").
+bool use_compiled_passes(const StateImpl* s);
+constexpr int kJitAutoMinQubits = 26;
+// Plan a gate list as qs_run would (adjoint: also the reverse sweep of
+// qs_grad_adjoint) and compile its pass kernels; *nkernels: how many.
+Status precompile_passes(int n, int dtype, const std::vector<XGate>& gates, bool adjoint,
+                         int* nkernels);
+// The reverse sweep's gate list: U_j^dagger in reverse order.
+void reverse_daggered(const std::vector<XGate>& gates, std::vector<XGate>* rev);
 
 // ----------------------------------------------------------- adjoint
 Status run_adjoint(StateImpl* s, StateImpl* lam, const std::vector<XGate>& gates,

@@ -1,0 +1,839 @@
+// qs_jit.cpp -- fused passes compiled per pass shape at run time (hipRTC).
+//
+// The planner (qs_plan.cpp) turns a block of gates into a list of fused ops
+// over a register tile (qHiPSTER Sec. 4.4, Fig. 4: one memory round trip per
+// block).  The interpreter kernels in qs_fused.hip decode that list at run
+// time; this file instead writes one straight-line kernel per pass, with
+// every structural field of every op (kind, target register bit, where the
+// control lives, which tile bits the lanes and registers hold before and
+// after each LDS remap, the gradient slot) fixed in the source.  Only the
+// numbers stay data: gate matrices, phases and the phase-run tables are read
+// from the same uploaded op records the interpreter uses.  With nothing to
+// decode and no branch merges inside the tile's register arrays, the pass
+// issues little beyond the gate arithmetic itself, its remaps and its
+// loads and stores.
+//
+// Kernels are cached by their source text (which is the pass's shape), so a
+// circuit of the same form with new parameters -- the next step of a
+// variational loop -- or the same circuit run again launches without
+// compiling.  Missing kernels of one call are compiled together, spread over
+// host threads, before the call's first launch.
+#include <hip/hiprtc.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <fstream>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "qs_internal.h"
+
+namespace qs {
+
+namespace {
+
+// ------------------------------------------------------------ emitter
+
+struct Src {
+  std::string s;
+  void operator()(const char* fmt, ...) __attribute__((format(printf, 2, 3))) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    const int n = vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (n >= (int)sizeof buf) {
+      std::string big((size_t)n + 1, '\0');
+      va_start(ap, fmt);
+      vsnprintf(&big[0], big.size(), fmt, ap);
+      va_end(ap);
+      big.resize((size_t)n);
+      s += big;
+    } else {
+      s.append(buf, (size_t)n);
+    }
+    s += '\n';
+  }
+};
+
+// Device helpers shared by every generated kernel of a program.
+const char* kPrelude = R"(
+typedef double qs_d2 __attribute__((ext_vector_type(2)));
+typedef float qs_f2 __attribute__((ext_vector_type(2)));
+typedef float qs_f4 __attribute__((ext_vector_type(4)));
+struct QsOp { int kind, tgt, ctl, aux; double m[8]; };
+__device__ __forceinline__ int qs_swz128(int j) { return j ^ (((j >> 3) ^ (j >> 6) ^ (j >> 9)) & 7); }
+__device__ __forceinline__ int qs_swz64(int j) { return j ^ (((j >> 4) ^ (j >> 8) ^ (j >> 12)) & 15); }
+template <int CTRL>
+__device__ __forceinline__ double qs_dpp(double v) {
+  const unsigned long long b = (unsigned long long)__builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+// sum over a 16-lane row, every lane receives it (fixed order)
+__device__ __forceinline__ double qs_row_sum16(double v) {
+  v += qs_dpp<0x140>(v);
+  v += qs_dpp<0x141>(v);
+  v += qs_dpp<0x1B>(v);
+  v += qs_dpp<0xB1>(v);
+  return v;
+}
+// (X[A], X[B]) <- Q (X[A], X[B]) with coefficients c0..c3 in scope
+#define QS_U(XR, XI, A, B) { const R ar_ = XR[A], ai_ = XI[A], br_ = XR[B], bi_ = XI[B]; \
+  XR[A] = c0r * ar_ - c0i * ai_ + c1r * br_ - c1i * bi_; \
+  XI[A] = c0r * ai_ + c0i * ar_ + c1r * bi_ + c1i * br_; \
+  XR[B] = c2r * ar_ - c2i * ai_ + c3r * br_ - c3i * bi_; \
+  XI[B] = c2r * ai_ + c2i * ar_ + c3r * bi_ + c3i * br_; }
+// the same for a real matrix
+#define QS_UR(XR, XI, A, B) { const R ar_ = XR[A], ai_ = XI[A], br_ = XR[B], bi_ = XI[B]; \
+  XR[A] = c0r * ar_ + c1r * br_; XI[A] = c0r * ai_ + c1r * bi_; \
+  XR[B] = c2r * ar_ + c3r * br_; XI[B] = c2r * ai_ + c3r * bi_; }
+// X[A] *= (FR + i FI)
+#define QS_SC(XR, XI, A, FR, FI) { const R t_ = XR[A]; \
+  XR[A] = (FR) * t_ - (FI) * XI[A]; XI[A] = (FR) * XI[A] + (FI) * t_; }
+// (PR, PI) *= (DR + i DI)
+#define QS_CMUL(PR, PI, DR, DI) { const R t_ = PR * (DR) - PI * (DI); PI = PR * (DI) + PI * (DR); PR = t_; }
+// Im(conj(l) w)
+#define QS_IMC(LR, LI, WR, WI) ((double)(LR) * (double)(WI) - (double)(LI) * (double)(WR))
+)";
+
+// Tile-bit layout of one pass (the same values the interpreter receives in
+// FusedArgs and FMapDev).
+struct Geo {
+  int dtype, nreg, RA, T, L, lane0, es;
+  bool c64;
+};
+
+inline int swz(const Geo& g, int j) {
+  return g.c64 ? (j ^ (((j >> 4) ^ (j >> 8) ^ (j >> 12)) & 15))
+               : (j ^ (((j >> 3) ^ (j >> 6) ^ (j >> 9)) & 7));
+}
+
+// Byte offset in the remap buffer of register r's part of a tile position.
+int regoff(const Geo& g, const FMap& m, int r) {
+  int o = 0;
+  for (int k = 0; k < g.nreg; ++k)
+    if ((r >> k) & 1) o |= 1 << m.reg[k];
+  return swz(g, o) * g.es;
+}
+
+class PassEmitter {
+ public:
+  PassEmitter(const Plan& plan, const Pass& p, int n, int dtype, bool adj, bool pipe)
+      : plan_(plan), p_(p), n_(n), adj_(adj), pipe_(pipe && !adj) {
+    const FuseGeom G = fuse_geom(dtype);
+    g_.dtype = dtype;
+    g_.nreg = G.nreg;
+    g_.RA = 1 << G.nreg;
+    g_.T = G.T;
+    g_.L = G.L;
+    g_.lane0 = G.lane0;
+    g_.c64 = dtype == QS_C64;
+    g_.es = g_.c64 ? 8 : 16;
+  }
+
+  // Kernel text after its name; empty when the pass has a shape this
+  // generator does not take (the interpreter runs it then).
+  std::string body() {
+    if (!check()) return std::string();
+    emit();
+    return src_.s;
+  }
+
+ private:
+  const Plan& plan_;
+  const Pass& p_;
+  int n_;
+  bool adj_;
+  bool pipe_;  // software-pipelined tile loop (forward passes)
+  Geo g_;
+  Src src_;
+  std::vector<int> thr_off_emitted_;
+
+  int gq(int tb) const { return tb < g_.L ? tb : (int)p_.hpos[tb - g_.L]; }
+
+  bool check() const {
+    const FMap& ml = plan_.maps[p_.map_load];
+    const FMap& ms = plan_.maps[p_.map_store];
+    for (int i = 0; i < 6; ++i)
+      if (ml.thr[i] != g_.lane0 + i || ms.thr[i] != g_.lane0 + i) return false;
+    if (g_.c64 && (ml.reg[0] != 0 || ms.reg[0] != 0)) return false;
+    if (p_.nh > 8 || p_.ngrad > kAdjMaxSlots) return false;
+    for (int i = p_.op_first; i < p_.op_first + p_.nops; ++i) {
+      const int k = plan_.ops[i].kind & 255;
+      if (k != kOpRemap && k != kOpU && k != kOpDiag && k != kOpPhaseRun && k != kOpPhaseEntry)
+        return false;
+      if (adj_ && (k == kOpPhaseRun || k == kOpPhaseEntry)) return false;
+    }
+    return true;
+  }
+
+  // `var` = the global index base of tile `tilev`: the tile index with a 0
+  // bit inserted at every high tile qubit, above the low qubits.
+  void emit_base(const char* var, const char* tilev) {
+    src_("    unsigned long long %s = %s << %d;", var, tilev, g_.L);
+    for (int h = 0; h < p_.nh; ++h) {
+      const int P = p_.hpos[h];
+      src_("    %s = ((%s >> %d) << %d) | (%s & %lluull);", var, var, P, P + 1, var, (1ull << P) - 1ull);
+    }
+  }
+
+  bool has_remap() const {
+    for (int i = p_.op_first; i < p_.op_first + p_.nops; ++i)
+      if ((plan_.ops[i].kind & 255) == kOpRemap) return true;
+    return false;
+  }
+
+  // Uniform 64-bit offset (in amplitudes) of the wave bits of a mapping.
+  std::string wave_part(const FMap& m) const {
+    char b[160];
+    snprintf(b, sizeof b, "(((unsigned long long)(wv & 1)) << %d) | (((unsigned long long)(wv >> 1)) << %d)",
+             gq(m.thr[6]), gq(m.thr[7]));
+    return b;
+  }
+  unsigned long long reg_part(const FMap& m, int r) const {
+    unsigned long long o = 0;
+    for (int k = 0; k < g_.nreg; ++k)
+      if ((r >> k) & 1) o |= 1ull << gq(m.reg[k]);
+    return o;
+  }
+
+  // Condition text for a thread-bit spec: lane bits per lane, wave bits
+  // uniform.
+  static std::string thread_bit(int i) {
+    char b[64];
+    if (i < 6)
+      snprintf(b, sizeof b, "((lane >> %d) & 1)", i);
+    else
+      snprintf(b, sizeof b, "((wv >> %d) & 1)", i - 6);
+    return b;
+  }
+  static std::string outside_bit(int q) {
+    char b[64];
+    snprintf(b, sizeof b, "((int)(base >> %d) & 1)", q);
+    return b;
+  }
+
+  // Variable holding map m's swizzled byte offset of this thread's bits.
+  std::string thr_off(int mi) {
+    char name[32];
+    snprintf(name, sizeof name, "to%d", mi);
+    if (std::find(thr_off_emitted_.begin(), thr_off_emitted_.end(), mi) == thr_off_emitted_.end()) {
+      thr_off_emitted_.push_back(mi);
+      const FMap& m = plan_.maps[mi];
+      std::string e = "0";
+      for (int i = 0; i < 8; ++i) {
+        char b[64];
+        snprintf(b, sizeof b, " | (((tid >> %d) & 1) << %d)", i, (int)m.thr[i]);
+        e += b;
+      }
+      src_("    const int %s = %s(%s) * %d;", name, g_.c64 ? "qs_swz64" : "qs_swz128", e.c_str(), g_.es);
+    }
+    return name;
+  }
+
+  void emit_load(const char* XR, const char* XI, const char* ptr, const char* basev = "base") {
+    const FMap& m = plan_.maps[p_.map_load];
+    src_("    {");
+    src_("      const unsigned long long ub = %s | %s;", basev, wave_part(m).c_str());
+    if (!g_.c64) {
+      src_("      const qs_d2* pa = %s + ub;", ptr);
+      for (int r = 0; r < g_.RA; ++r) {
+        src_("      { const qs_d2 v = __builtin_nontemporal_load(pa + %lluull + lane); %s[%d] = v.x; %s[%d] = v.y; }",
+             reg_part(m, r), XR, r, XI, r);
+      }
+    } else {
+      src_("      const qs_f4* pa = %s + (ub >> 1);", ptr);
+      for (int r = 0; r < g_.RA; r += 2) {
+        src_("      { const qs_f4 v = __builtin_nontemporal_load(pa + %lluull + lane); %s[%d] = v.x; %s[%d] = v.y; "
+             "%s[%d] = v.z; %s[%d] = v.w; }",
+             reg_part(m, r) >> 1, XR, r, XI, r, XR, r + 1, XI, r + 1);
+      }
+    }
+    src_("    }");
+  }
+
+  void emit_store(const char* XR, const char* XI, const char* ptr) {
+    const FMap& m = plan_.maps[p_.map_store];
+    src_("    {");
+    src_("      const unsigned long long ub = base | %s;", wave_part(m).c_str());
+    if (!g_.c64) {
+      src_("      qs_d2* pa = %s + ub;", ptr);
+      for (int r = 0; r < g_.RA; ++r)
+        src_("      __builtin_nontemporal_store(qs_d2{%s[%d], %s[%d]}, pa + %lluull + lane);", XR, r, XI, r,
+             reg_part(m, r));
+    } else {
+      src_("      qs_f4* pa = %s + (ub >> 1);", ptr);
+      for (int r = 0; r < g_.RA; r += 2)
+        src_("      __builtin_nontemporal_store(qs_f4{%s[%d], %s[%d], %s[%d], %s[%d]}, pa + %lluull + lane);", XR,
+             r, XI, r, XR, r + 1, XI, r + 1, reg_part(m, r) >> 1);
+    }
+    src_("    }");
+  }
+
+  void emit_remap_tile(const char* XR, const char* XI, int mo, int mn) {
+    const std::string to = thr_off(mo), tn = thr_off(mn);
+    const char* VE = g_.c64 ? "qs_f2" : "qs_d2";
+    src_("    {");
+    for (int r = 0; r < g_.RA; ++r)
+      src_("      *(%s*)(lb + (%s ^ %d)) = %s{%s[%d], %s[%d]};", VE, to.c_str(), regoff(g_, plan_.maps[mo], r), VE,
+           XR, r, XI, r);
+    src_("      __syncthreads();");
+    for (int r = 0; r < g_.RA; ++r)
+      src_("      { const %s v = *(const %s*)(lb + (%s ^ %d)); %s[%d] = v.x; %s[%d] = v.y; }", VE, VE, tn.c_str(),
+           regoff(g_, plan_.maps[mn], r), XR, r, XI, r);
+    src_("      __syncthreads();");
+    src_("    }");
+  }
+
+  // Pairs (r, r | 2^k) whose register control bit (creg >= 0) is 1.
+  void pairs(int k, int creg, std::vector<std::pair<int, int>>* out) const {
+    for (int r = 0; r < g_.RA; ++r) {
+      if (r & (1 << k)) continue;
+      if (creg >= 0 && !((r >> creg) & 1)) continue;
+      out->push_back({r, r | (1 << k)});
+    }
+  }
+
+  // Coefficients c0..c3 of op i's matrix; `sel` (a lane condition) or
+  // empty: lanes where it is 0 take the identity.
+  void emit_coeffs(int i, bool real, const std::string& sel) {
+    src_("      const double* m_ = %s->m;", opref(i).c_str());
+    static const char* nm[8] = {"c0r", "c0i", "c1r", "c1i", "c2r", "c2i", "c3r", "c3i"};
+    if (!sel.empty()) src_("      const bool on_ = %s;", sel.c_str());
+    for (int e = 0; e < 8; ++e) {
+      if (real && (e & 1)) continue;
+      const char* id = (e == 0 || e == 6) ? "(R)1" : "(R)0";
+      if (sel.empty()) {
+        src_("      const R %s = (R)m_[%d];", nm[e], e);
+      } else {
+        // loaded first, then selected: a select around the load itself
+        // becomes a branch per coefficient
+        src_("      const R %s_ld = (R)m_[%d];", nm[e], e);
+        src_("      const R %s = on_ ? %s_ld : %s;", nm[e], nm[e], id);
+      }
+    }
+  }
+
+  // The op record of op i as an SGPR pointer released one op ahead: the
+  // empty asm keeps the compiler from hoisting every op's coefficient loads
+  // to the top of the kernel (which runs out of scalar registers and spills
+  // them into vector-register lanes), while still letting the next op's
+  // loads overlap the current op's arithmetic.
+  std::string opref(int i) const {
+    char b[32];
+    snprintf(b, sizeof b, "op%d_", i - p_.op_first);
+    return b;
+  }
+  void release_op(int i) {
+    if (i >= p_.op_first + p_.nops) return;
+    src_("    const QsOp* %s = ops + %d;", opref(i).c_str(), i - p_.op_first);
+    src_("    asm volatile(\"\" : \"+s\"(%s));", opref(i).c_str());
+  }
+
+  void emit_u(int i) {
+    const FOp& op = plan_.ops[i];
+    const int k = op.tgt;
+    const int cw = op.ctl >> 8, ci = op.ctl & 255;
+    const bool real = op.m[1] == 0.0 && op.m[3] == 0.0 && op.m[5] == 0.0 && op.m[7] == 0.0;
+    const int pauli = (op.kind >> 8) & 255;
+    src_("    {  // op %d: U on register bit %d, control %d/%d%s", i - p_.op_first, k, cw, ci, real ? ", real" : "");
+    std::string cond, sel;
+    if (cw == kInThread) (ci < 6 ? sel : cond) = thread_bit(ci);
+    if (cw == kOutside) cond = outside_bit(ci);
+    if (adj_ && op.aux >= 0) {
+      // rotation (never controlled): Im<lambda|P|psi> before U^dagger
+      std::vector<std::pair<int, int>> pr;
+      pairs(k, -1, &pr);
+      src_("      double g_ = 0.0;");
+      for (auto& q : pr) {
+        const int a = q.first, b = q.second;
+        if (pauli == 1)  // X psi = (a1, a0)
+          src_("      g_ += QS_IMC(yr[%d], yi[%d], xr[%d], xi[%d]) + QS_IMC(yr[%d], yi[%d], xr[%d], xi[%d]);", a, a, b,
+               b, b, b, a, a);
+        else  // Y psi = (-i a1, i a0)
+          src_("      g_ += QS_IMC(yr[%d], yi[%d], xi[%d], -xr[%d]) + QS_IMC(yr[%d], yi[%d], -xi[%d], xr[%d]);", a,
+               a, b, b, b, b, a, a);
+      }
+      emit_grad_store(op.aux);
+    }
+    if (!cond.empty()) src_("      if (%s) {", cond.c_str());
+    emit_coeffs(i, real, sel);
+    std::vector<std::pair<int, int>> pr;
+    pairs(k, cw == kInReg ? ci : -1, &pr);
+    for (auto& q : pr) {
+      src_("      %s(xr, xi, %d, %d)", real ? "QS_UR" : "QS_U", q.first, q.second);
+      if (adj_) src_("      %s(yr, yi, %d, %d)", real ? "QS_UR" : "QS_U", q.first, q.second);
+    }
+    if (!cond.empty()) src_("      }");
+    src_("    }");
+  }
+
+  void emit_grad_store(int slot) {
+    src_("      g_ = qs_row_sum16(g_);");
+    src_("      if ((tid & 15) == 0) acc[%d + (tid >> 4)] += g_;", slot * 16);
+  }
+
+  // Registers r whose target / control conditions hold get factor (fr, fi);
+  // which registers take d1 and which d0 follows the target spec.
+  void emit_diag(int i) {
+    const FOp& op = plan_.ops[i];
+    const int tw = op.tgt >> 8, tix = op.tgt & 255;
+    const int cw = op.ctl >> 8, ci = op.ctl & 255;
+    const bool phase = op.m[0] == 1.0 && op.m[1] == 0.0;
+    src_("    {  // op %d: diagonal, target %d/%d, control %d/%d%s", i - p_.op_first, tw, tix, cw, ci,
+         phase ? ", phase" : "");
+    src_("      const double* m_ = %s->m;", opref(i).c_str());
+    if (adj_ && op.aux >= 0) {
+      // RZ: Im<lambda|Z|psi>, sign by the target bit
+      src_("      double g_ = 0.0;");
+      if (tw == kInReg) {
+        for (int r = 0; r < g_.RA; ++r)
+          src_("      g_ %s= QS_IMC(yr[%d], yi[%d], xr[%d], xi[%d]);", ((r >> tix) & 1) ? "-" : "+", r, r, r, r);
+      } else {
+        src_("      {");
+        src_("        double s_ = 0.0;");
+        for (int r = 0; r < g_.RA; ++r) src_("        s_ += QS_IMC(yr[%d], yi[%d], xr[%d], xi[%d]);", r, r, r, r);
+        src_("        g_ = %s ? -s_ : s_;", tw == kInThread ? thread_bit(tix).c_str() : outside_bit(tix).c_str());
+        src_("      }");
+      }
+      emit_grad_store(op.aux);
+    }
+    std::string cond, csel;
+    if (cw == kInThread) (ci < 6 ? csel : cond) = thread_bit(ci);
+    if (cw == kOutside) cond = outside_bit(ci);
+    const int creg = cw == kInReg ? ci : -1;
+    if (tw == kOutside && phase) cond = cond.empty() ? outside_bit(tix) : cond + " && " + outside_bit(tix);
+    if (!cond.empty()) src_("      if (%s) {", cond.c_str());
+    src_("      const R d0r = (R)m_[0], d0i = (R)m_[1], d1r = (R)m_[6], d1i = (R)m_[7];");
+    auto scale_regs = [&](const char* fr, const char* fi, int want_bit /* -1 any */) {
+      for (int r = 0; r < g_.RA; ++r) {
+        if (creg >= 0 && !((r >> creg) & 1)) continue;
+        if (want_bit >= 0 && ((r >> tix) & 1) != want_bit) continue;
+        src_("      QS_SC(xr, xi, %d, %s, %s)", r, fr, fi);
+        if (adj_) src_("      QS_SC(yr, yi, %d, %s, %s)", r, fr, fi);
+      }
+    };
+    if (tw == kInReg) {
+      // per register: d1 where the target bit is 1, d0 (unless a phase) where 0
+      if (csel.empty()) {
+        scale_regs("d1r", "d1i", 1);
+        if (!phase) scale_regs("d0r", "d0i", 0);
+      } else {
+        src_("      const bool on_ = %s;", csel.c_str());
+        src_("      const R e1r = on_ ? d1r : (R)1, e1i = on_ ? d1i : (R)0;");
+        scale_regs("e1r", "e1i", 1);
+        if (!phase) {
+          src_("      const R e0r = on_ ? d0r : (R)1, e0i = on_ ? d0i : (R)0;");
+          scale_regs("e0r", "e0i", 0);
+        }
+      }
+    } else {
+      // one factor for the whole thread: the target bit is a thread bit or
+      // lies outside the tile
+      if (tw == kOutside && phase) {
+        src_("      R fr_ = d1r, fi_ = d1i;");
+      } else {
+        const std::string b = tw == kInThread ? thread_bit(tix) : outside_bit(tix);
+        src_("      R fr_ = %s ? d1r : d0r, fi_ = %s ? d1i : d0i;", b.c_str(), b.c_str());
+      }
+      if (!csel.empty()) {
+        src_("      const bool on_ = %s;", csel.c_str());
+        src_("      fr_ = on_ ? fr_ : (R)1; fi_ = on_ ? fi_ : (R)0;");
+      }
+      scale_regs("fr_", "fi_", -1);
+    }
+    if (!cond.empty()) src_("      }");
+    src_("    }");
+  }
+
+  // A phase run (forward passes only): per-lane product of the run's
+  // phases, then the target-bit-1 amplitudes scaled once.
+  int emit_run(int i) {
+    const FOp& h = plan_.ops[i];
+    const int tw = h.tgt >> 8, tix = h.tgt & 255;
+    src_("    {  // op %d: phase run of %d explicit entries, target %d/%d", i - p_.op_first, h.aux, tw, tix);
+    src_("      const QsOp* h_ = %s;", opref(i).c_str());
+    if (h.m[4] != 0.0) {
+      src_("      R pr = ttr%d, pi = tti%d;", i - p_.op_first, i - p_.op_first);
+    } else {
+      src_("      R pr = (R)1, pi = (R)0;");
+    }
+    for (int e = 1; e <= h.aux; ++e) {
+      const FOp& en = plan_.ops[i + e];
+      const int ew = en.ctl >> 8, eb = en.ctl & 255;
+      src_("      {");
+      src_("        const double* m_ = ops[%d].m;", i + e - p_.op_first);  // entries: read with the run
+      if (ew == kNoBit) {
+        src_("        const R fr = (R)m_[6], fi = (R)m_[7];");
+      } else {
+        const std::string b = ew == kInThread ? thread_bit(eb) : outside_bit(eb);
+        src_("        const bool on_ = %s;", b.c_str());
+        src_("        const R fr = on_ ? (R)m_[6] : (R)1, fi = on_ ? (R)m_[7] : (R)0;");
+      }
+      src_("        QS_CMUL(pr, pi, fr, fi)");
+      src_("      }");
+    }
+    if (h.m[2] != 0.0) {
+      src_("      {");
+      src_("        const int lb_ = (int)h_->m[1];");
+      src_("        const double* tlo = (const double*)(maps + (unsigned long long)h_->m[0]);");
+      src_("        const double* thi = tlo + 2 * (1ull << lb_);");
+      src_("        const unsigned long long lo = tile & ((1ull << lb_) - 1ull), hi = tile >> lb_;");
+      src_("        QS_CMUL(pr, pi, (R)tlo[2 * lo], (R)tlo[2 * lo + 1])");
+      src_("        QS_CMUL(pr, pi, (R)thi[2 * hi], (R)thi[2 * hi + 1])");
+      src_("      }");
+    }
+    if (tw == kInReg) {
+      for (int r = 0; r < g_.RA; ++r)
+        if ((r >> tix) & 1) src_("      QS_SC(xr, xi, %d, pr, pi)", r);
+    } else if (tw == kInThread && tix < 6) {
+      src_("      const bool b_ = %s;", thread_bit(tix).c_str());
+      src_("      const R fr_ = b_ ? pr : (R)1, fi_ = b_ ? pi : (R)0;");
+      for (int r = 0; r < g_.RA; ++r) src_("      QS_SC(xr, xi, %d, fr_, fi_)", r);
+    } else {
+      const std::string b = tw == kInThread ? thread_bit(tix) : outside_bit(tix);
+      src_("      if (%s) {", b.c_str());
+      for (int r = 0; r < g_.RA; ++r) src_("        QS_SC(xr, xi, %d, pr, pi)", r);
+      src_("      }");
+    }
+    src_("    }");
+    return h.aux;
+  }
+
+  void emit() {
+    const char* VT = g_.c64 ? "qs_f4" : "qs_d2";
+    if (adj_)
+      src_("(%s* __restrict__ qa, %s* __restrict__ ql, const QsOp* __restrict__ ops, const char* __restrict__ maps, "
+           "double* __restrict__ part, unsigned long long ntiles) {",
+           VT, VT);
+    else
+      src_("(%s* __restrict__ qa, const QsOp* __restrict__ ops, const char* __restrict__ maps, "
+           "unsigned long long ntiles) {",
+           VT);
+    src_("  typedef %s R;", g_.c64 ? "float" : "double");
+    src_("  const int tid = threadIdx.x;");
+    src_("  const int lane = tid & 63;");
+    src_("  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);");
+    const bool remaps = has_remap();
+    if (remaps) {
+      src_("  __shared__ %s lds[%d];", g_.c64 ? "qs_f2" : "qs_d2", g_.RA * 256);
+      src_("  char* lb = (char*)lds;");
+    }
+    const int ngrad = adj_ ? p_.ngrad : 0;
+    if (ngrad > 0) {
+      src_("  __shared__ double acc[%d];", ngrad * 16);
+      src_("  for (int i = tid; i < %d; i += 256) acc[i] = 0.0;", ngrad * 16);
+      src_("  __syncthreads();");
+    }
+    src_("  R xr[%d], xi[%d];", g_.RA, g_.RA);
+    if (adj_) src_("  R yr[%d], yi[%d];", g_.RA, g_.RA);
+    if (pipe_) {
+      // the next tile's amplitudes are loaded while this one is computed
+      src_("  R nr[%d], ni[%d];", g_.RA, g_.RA);
+      src_("  if ((unsigned long long)blockIdx.x < ntiles) {");
+      emit_base("nbase", "(unsigned long long)blockIdx.x");
+      emit_load("nr", "ni", "qa", "nbase");
+      src_("  }");
+    }
+    src_("  for (unsigned long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {");
+    emit_base("base", "tile");
+    // per-thread phase-run tables: read before this iteration's tile loads
+    // so that waiting for them never waits for the tile
+    for (int i = p_.op_first; i < p_.op_first + p_.nops; ++i) {
+      const FOp& op = plan_.ops[i];
+      if ((op.kind & 255) != kOpPhaseRun) continue;
+      if (op.m[4] != 0.0) {
+        const int j = i - p_.op_first;
+        src_("    const double* tt%d = (const double*)(maps + (unsigned long long)ops[%d].m[3]);", j, j);
+        src_("    const R ttr%d = (R)tt%d[2 * tid], tti%d = (R)tt%d[2 * tid + 1];", j, j, j, j);
+      }
+      i += op.aux;
+    }
+    if (pipe_) {
+      for (int r = 0; r < g_.RA; ++r) src_("    xr[%d] = nr[%d]; xi[%d] = ni[%d];", r, r, r, r);
+      src_("    if (tile + gridDim.x < ntiles) {");
+      emit_base("nbase", "(tile + gridDim.x)");
+      emit_load("nr", "ni", "qa", "nbase");
+      src_("    }");
+    } else {
+      emit_load("xr", "xi", "qa");
+    }
+    if (adj_) emit_load("yr", "yi", "ql");
+    // op records: op i's pointer is released at the start of op i - 1
+    int released = p_.op_first;
+    auto release_upto = [&](int last) {
+      for (; released <= last && released < p_.op_first + p_.nops; ++released) {
+        const int k = plan_.ops[released].kind & 255;
+        if (k == kOpU || k == kOpDiag || k == kOpPhaseRun) release_op(released);
+      }
+    };
+    for (int i = p_.op_first; i < p_.op_first + p_.nops; ++i) {
+      const FOp& op = plan_.ops[i];
+      const int kind = op.kind & 255;
+      const int next = kind == kOpPhaseRun ? i + op.aux + 1 : i + 1;
+      release_upto(i);
+      // the next op that reads a record
+      for (int j = next; j < p_.op_first + p_.nops; ++j) {
+        const int k = plan_.ops[j].kind & 255;
+        if (k == kOpU || k == kOpDiag || k == kOpPhaseRun) {
+          release_upto(j);
+          break;
+        }
+        if (k == kOpPhaseEntry) continue;
+      }
+      if (kind == kOpRemap) {
+        src_("    // op %d: remap %d -> %d", i - p_.op_first, op.aux, op.tgt);
+        emit_remap_tile("xr", "xi", op.aux, op.tgt);
+        if (adj_) emit_remap_tile("yr", "yi", op.aux, op.tgt);
+      } else if (kind == kOpU) {
+        emit_u(i);
+      } else if (kind == kOpDiag) {
+        emit_diag(i);
+      } else if (kind == kOpPhaseRun) {
+        i += emit_run(i);
+      }
+    }
+    emit_store("xr", "xi", "qa");
+    if (adj_) emit_store("yr", "yi", "ql");
+    src_("  }");
+    if (ngrad > 0) {
+      src_("  __syncthreads();");
+      src_("  if (tid < %d) {", ngrad);
+      src_("    double s = 0.0;");
+      src_("    for (int r = 0; r < 16; ++r) s += acc[tid * 16 + r];");
+      src_("    part[(unsigned long long)tid * gridDim.x + blockIdx.x] = s;");
+      src_("  }");
+    }
+    src_("}");
+  }
+};
+
+// ------------------------------------------------------------ cache
+
+struct JitProgram {
+  std::string code;                  // code object
+  std::vector<hipModule_t> modules;  // per device (null until loaded)
+};
+struct JitEntry {
+  int program = -1;
+  std::string name;
+  std::vector<hipFunction_t> fn;  // per device
+};
+
+std::mutex g_mu;
+std::unordered_map<std::string, int> g_index;  // kernel text -> entry
+std::vector<JitEntry> g_entries;
+std::vector<JitProgram> g_programs;
+JitStats g_stats;
+
+// Optional occupancy target for generated kernels (QS_JIT_WAVES=<waves per
+// SIMD>), part of every cache key through the kernel text.
+std::string jit_kernel_attrs() {
+  const char* e = getenv("QS_JIT_WAVES");
+  const int w = e ? atoi(e) : 0;
+  if (w <= 0) return std::string();
+  char b[64];
+  snprintf(b, sizeof b, "__attribute__((amdgpu_waves_per_eu(%d))) ", w);
+  return b;
+}
+
+uint64_t fnv1a(const std::string& s) {
+  uint64_t h = 1469598103934665603ull;
+  for (unsigned char c : s) {
+    h ^= c;
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+struct CompileJob {
+  std::vector<std::pair<std::string, std::string>> kernels;  // (name, text)
+  std::string code, error;
+  double seconds = 0.0;
+};
+
+void compile_job(CompileJob* job) {
+  const auto t0 = std::chrono::steady_clock::now();
+  std::string src = kPrelude;
+  for (auto& k : job->kernels) {
+    src += "extern \"C\" __global__ void __launch_bounds__(256) ";
+    src += jit_kernel_attrs();
+    src += k.first;
+    src += k.second;
+  }
+  const char* dump = getenv("QS_JIT_DUMP");
+  if (dump && *dump) {
+    std::ofstream(std::string(dump) + "/" + job->kernels[0].first + ".hip") << src;
+  }
+  hiprtcProgram prog;
+  hiprtcResult r = hiprtcCreateProgram(&prog, src.c_str(), "qs_pass.hip", 0, nullptr, nullptr);
+  if (r != HIPRTC_SUCCESS) {
+    job->error = std::string("hiprtcCreateProgram: ") + hiprtcGetErrorString(r);
+    return;
+  }
+  const char* opts[] = {"--offload-arch=gfx950", "-O3", "-ffp-contract=fast", "-Xclang", "-target-feature",
+                        "-Xclang", "-packed-fp32-ops"};
+  r = hiprtcCompileProgram(prog, (int)(sizeof opts / sizeof opts[0]), opts);
+  if (r != HIPRTC_SUCCESS) {
+    size_t n = 0;
+    hiprtcGetProgramLogSize(prog, &n);
+    std::string log(n, '\0');
+    if (n) hiprtcGetProgramLog(prog, &log[0]);
+    if (log.size() > 2000) log.resize(2000);
+    job->error = std::string("hiprtcCompileProgram: ") + hiprtcGetErrorString(r) + "\n" + log;
+    hiprtcDestroyProgram(&prog);
+    return;
+  }
+  size_t sz = 0;
+  hiprtcGetCodeSize(prog, &sz);
+  job->code.resize(sz);
+  hiprtcGetCode(prog, &job->code[0]);
+  hiprtcDestroyProgram(&prog);
+  if (dump && *dump) {
+    std::ofstream(std::string(dump) + "/" + job->kernels[0].first + ".co", std::ios::binary)
+        .write(job->code.data(), (std::streamsize)job->code.size());
+  }
+  job->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+int compile_threads() {
+  const char* e = getenv("QS_JIT_THREADS");
+  int t = e ? atoi(e) : 0;
+  if (t <= 0) t = (int)std::thread::hardware_concurrency();
+  return std::max(1, std::min(t, 16));
+}
+
+// Make sure every text in `texts` has a cache entry (compiling the missing
+// ones); entry indices into *idx.
+Status ensure_compiled(const std::vector<std::string>& texts, std::vector<int>* idx) {
+  std::vector<std::string> missing;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (const std::string& t : texts)
+      if (!g_index.count(t) && std::find(missing.begin(), missing.end(), t) == missing.end())
+        missing.push_back(t);
+  }
+  if (!missing.empty()) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const int nthreads = std::min<int>(compile_threads(), (int)missing.size());
+    std::vector<CompileJob> jobs((size_t)nthreads);
+    for (size_t i = 0; i < missing.size(); ++i) {
+      char name[48];
+      snprintf(name, sizeof name, "qs_pass_%016llx", (unsigned long long)fnv1a(missing[i]));
+      jobs[i % (size_t)nthreads].kernels.push_back({name, missing[i]});
+    }
+    std::vector<std::thread> th;
+    for (int j = 1; j < nthreads; ++j) th.emplace_back(compile_job, &jobs[(size_t)j]);
+    compile_job(&jobs[0]);
+    for (auto& t : th) t.join();
+    for (auto& j : jobs)
+      if (!j.error.empty()) return Status{QS_EHIP, "fused-pass compile failed: " + j.error};
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto& j : jobs) {
+      const int pi = (int)g_programs.size();
+      g_programs.push_back(JitProgram{std::move(j.code), {}});
+      for (auto& k : j.kernels) {
+        if (g_index.count(k.second)) continue;
+        JitEntry e;
+        e.program = pi;
+        e.name = k.first;
+        g_index[k.second] = (int)g_entries.size();
+        g_entries.push_back(std::move(e));
+      }
+    }
+    g_stats.kernels += (long long)missing.size();
+    g_stats.compile_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  idx->clear();
+  for (const std::string& t : texts) idx->push_back(g_index.at(t));
+  return Status::ok();
+}
+
+Status function_on(int entry, int dev, hipFunction_t* out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  JitEntry& e = g_entries[(size_t)entry];
+  if ((int)e.fn.size() <= dev) e.fn.resize((size_t)dev + 1, nullptr);
+  if (!e.fn[(size_t)dev]) {
+    JitProgram& p = g_programs[(size_t)e.program];
+    if ((int)p.modules.size() <= dev) p.modules.resize((size_t)dev + 1, nullptr);
+    if (!p.modules[(size_t)dev]) {
+      hipModule_t m = nullptr;
+      hipError_t err = hipModuleLoadData(&m, p.code.data());
+      if (err != hipSuccess) return hip_status(err, "load fused-pass module");
+      p.modules[(size_t)dev] = m;
+      ++g_stats.modules_loaded;
+    }
+    hipFunction_t f = nullptr;
+    hipError_t err = hipModuleGetFunction(&f, p.modules[(size_t)dev], e.name.c_str());
+    if (err != hipSuccess) return hip_status(err, "fused-pass kernel lookup");
+    e.fn[(size_t)dev] = f;
+  }
+  *out = e.fn[(size_t)dev];
+  return Status::ok();
+}
+
+}  // namespace
+
+bool jit_pipelined(bool adjoint) {
+  if (adjoint) return false;
+  const char* e = getenv("QS_JIT_PIPE");
+  return e && atoi(e) > 0;
+}
+
+int jit_pipe_wg_per_cu() {
+  const char* e = getenv("QS_JIT_PIPE_WG");
+  const int v = e ? atoi(e) : 0;
+  return v > 0 ? v : 4;
+}
+
+std::string jit_pass_text(const Plan& plan, const Pass& p, int n, int dtype, bool adjoint) {
+  PassEmitter em(plan, p, n, dtype, adjoint, jit_pipelined(adjoint));
+  std::string b = em.body();
+  if (b.empty()) return b;
+  return "/*" + jit_kernel_attrs() + "*/" + b;
+}
+
+Status jit_prepare(const Plan& plan, int n, int dtype, bool adjoint, std::vector<JitPass>* out) {
+  out->assign(plan.passes.size(), JitPass{});
+  std::vector<std::string> texts;
+  std::vector<int> which;
+  for (size_t i = 0; i < plan.passes.size(); ++i) {
+    if (plan.passes[i].kind != kPassFused) continue;
+    std::string t = jit_pass_text(plan, plan.passes[i], n, dtype, adjoint);
+    if (t.empty()) continue;
+    texts.push_back(std::move(t));
+    which.push_back((int)i);
+  }
+  std::vector<int> idx;
+  Status st = ensure_compiled(texts, &idx);
+  if (!st.good()) return st;
+  for (size_t j = 0; j < which.size(); ++j) {
+    (*out)[(size_t)which[j]].entry = idx[j];
+    (*out)[(size_t)which[j]].persistent = jit_pipelined(adjoint);
+  }
+  return Status::ok();
+}
+
+Status jit_function(const JitPass& jp, int device, hipFunction_t* fn) {
+  if (jp.entry < 0) return Status{QS_EINVAL, "pass has no compiled kernel"};
+  return function_on(jp.entry, device, fn);
+}
+
+JitStats jit_stats() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  JitStats s = g_stats;
+  s.cached = (long long)g_entries.size();
+  return s;
+}
+
+}  // namespace qs

@@ -29,6 +29,8 @@ QS_ADJ_STATE_IS_FINAL = 1
 QS_BATCH_MAX_QUBITS = 24
 QS_KQ_MAX = 5
 QS_NOALLOC_SCRATCH_BYTES = 2048 * 35 * 8 + 35 * 8
+QS_EXEC_AUTO, QS_EXEC_INTERPRETED, QS_EXEC_COMPILED = 0, 1, 2
+QS_PRECOMPILE_ADJOINT = 1
 
 # Mirror of `struct qs_op` (80 bytes).
 QS_OP_DTYPE = np.dtype([("kind", "<i4"), ("target", "<i4"), ("control", "<i4"),
@@ -39,7 +41,8 @@ EXPORTED = ("qs_version", "qs_strerror", "qs_last_error", "qs_create", "qs_destr
             "qs_probabilities", "qs_expect_pauli", "qs_apply_pauli_sum", "qs_grad_adjoint",
             "qs_stream_copy", "qs_plan", "qs_batch_create", "qs_batch_run",
             "qs_batch_destroy", "qs_apply_kq", "qs_permute_qubits", "qs_plan_reorder",
-            "qs_run_reordered", "qs_set_grid_limit", "qs_probabilities_noalloc")
+            "qs_run_reordered", "qs_set_grid_limit", "qs_probabilities_noalloc",
+            "qs_set_fused_exec", "qs_precompile", "qs_get_jit_stats")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1601_07195_amd.build`")
@@ -55,6 +58,16 @@ _L.qs_create.argtypes = [_i, _i, _vp, _sz, _vp, ctypes.POINTER(_vp)]
 _L.qs_destroy.argtypes = [_vp]
 _L.qs_set_stream.argtypes = [_vp, _vp]
 _L.qs_set_grid_limit.argtypes = [_vp, _i]
+_L.qs_set_fused_exec.argtypes = [_vp, _i]
+_L.qs_precompile.argtypes = [_i, _i, _vp, _i, _dp, _i, _i, _vp]
+
+
+class QSJitStats(ctypes.Structure):
+    _fields_ = [("kernels_compiled", ctypes.c_int64), ("kernels_cached", ctypes.c_int64),
+                ("modules_loaded", ctypes.c_int64), ("compile_seconds", ctypes.c_double)]
+
+
+_L.qs_get_jit_stats.argtypes = [ctypes.POINTER(QSJitStats)]
 _L.qs_init_basis.argtypes = [_vp, _u64]
 _L.qs_apply_1q.argtypes = [_vp, _i, _dp]
 _L.qs_apply_cu.argtypes = [_vp, _i, _i, _dp]
@@ -300,6 +313,26 @@ def qs_plan(n: int, dtype: int, ops, theta=None, flags: int = 0):
     return d, order, pass_of
 
 
+def qs_set_fused_exec(h: int, mode: int) -> None:
+    _check(_L.qs_set_fused_exec(h, mode), "qs_set_fused_exec")
+
+
+def qs_precompile(n: int, dtype: int, ops, theta=None, flags: int = 0) -> int:
+    """Host-only: compile the pass kernels a run of `ops` needs; returns their count."""
+    a = ops_array(ops)
+    th = _f64(theta) if theta is not None else None
+    nk = np.zeros(1, dtype=np.int32)
+    _check(_L.qs_precompile(n, dtype, _ptr(a), len(a), _ptr(th), 0 if th is None else len(th), flags,
+                            _ptr(nk)), "qs_precompile")
+    return int(nk[0])
+
+
+def qs_get_jit_stats() -> dict:
+    st = QSJitStats()
+    _check(_L.qs_get_jit_stats(ctypes.byref(st)), "qs_get_jit_stats")
+    return {f: getattr(st, f) for f, _ in QSJitStats._fields_}
+
+
 def qs_permute_qubits(h: int, perm) -> None:
     """Relabel qubit q as perm[q] in place (state reordering, Sec. 6)."""
     p = np.ascontiguousarray(perm, dtype=np.int32)
@@ -429,6 +462,10 @@ class State:
 
     def set_grid_limit(self, max_workgroups: int) -> "State":
         qs_set_grid_limit(self.handle, max_workgroups)
+        return self
+
+    def set_fused_exec(self, mode: int) -> "State":
+        qs_set_fused_exec(self.handle, mode)
         return self
 
     def init_basis(self, index: int = 0) -> "State":

@@ -224,8 +224,10 @@ def test_config4_full_batch_against_oracle(Q, batch_workload, name):
     print(f"config4 {name}: circuits {sample} (n {ns}); max |dE| {worst_e:.2e}, max |dg| {worst_g:.2e}")
 
 
+@pytest.mark.parametrize("mode", ["interpreted", "compiled"])
 @pytest.mark.parametrize("name,n,layers", [("c128", 12, 6), ("c64", 13, 6)])
-def test_adjoint_passes_split_at_the_gradient_slot_limit(Q, name, n, layers):
+def test_adjoint_passes_split_at_the_gradient_slot_limit(Q, name, n, layers, mode, monkeypatch):
+    monkeypatch.setenv("QS_FUSED_EXEC", mode)
     """Every rotation of these circuits fits one fused pass by its qubits,
     but a pass carries at most 64 gradient slots, so the sweep splits; all
     2nL parameters are checked."""
@@ -242,9 +244,11 @@ def test_adjoint_passes_split_at_the_gradient_slot_limit(Q, name, n, layers):
         assert abs(e - re) <= 1e-4 * scale and np.abs(g - rg).max() <= 1e-4 * scale
 
 
+@pytest.mark.parametrize("mode", ["interpreted", "compiled"])
 @pytest.mark.parametrize("name,n,limit", [("c128", 14, 3), ("c128", 15, 5), ("c64", 14, 1),
                                           ("c64", 15, 3)])
-def test_persistent_grid_forced_by_a_grid_limit(Q, name, n, limit):
+def test_persistent_grid_forced_by_a_grid_limit(Q, name, n, limit, mode, monkeypatch):
+    monkeypatch.setenv("QS_FUSED_EXEC", mode)
     """A grid limit below the tile count makes each workgroup loop over
     several tiles (the branch large states take), in the forward passes and
     in the reverse sweep, whose gradient partials then accumulate across

@@ -16,6 +16,15 @@ from tests.gpu_util import Q, random_state, rounded_input, to_gpu_state  # noqa:
 pytestmark = pytest.mark.gpu
 
 
+@pytest.fixture(params=["interpreted", "compiled"], autouse=True)
+def fused_exec(request, monkeypatch):
+    """Every test here runs twice: fused passes on the interpreter kernels and
+    on kernels compiled per pass shape (QS_FUSED_EXEC drives states left in
+    QS_EXEC_AUTO)."""
+    monkeypatch.setenv("QS_FUSED_EXEC", request.param)
+    return request.param
+
+
 def dt(Q, name):
     return Q.QS_C128 if name == "c128" else Q.QS_C64
 

@@ -20,6 +20,15 @@ from tests.gpu_util import Q  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 
+
+@pytest.fixture(params=["interpreted", "compiled"], autouse=True)
+def fused_exec(request, monkeypatch):
+    """Every test here runs twice: fused passes on the interpreter kernels and
+    on kernels compiled per pass shape (QS_FUSED_EXEC drives states left in
+    QS_EXEC_AUTO)."""
+    monkeypatch.setenv("QS_FUSED_EXEC", request.param)
+    return request.param
+
 N = 24
 
 

@@ -1,0 +1,65 @@
+"""CPU-only checks of the compiled fused passes: the generator writes a
+kernel for every fused pass of representative gate lists and hipRTC
+compiles them for gfx950 (no GPU needed); kernels are cached by pass shape,
+so the same circuit form with other angles compiles nothing new."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import circuits as C
+
+
+@pytest.fixture(scope="module")
+def Q():
+    import paper_1601_07195_amd.qs as Q
+    return Q
+
+
+def _plan_fused(Q, n, dtype, ops, theta=None):
+    info, _, _ = Q.qs_plan(n, dtype, ops, theta)
+    return info["fused"]
+
+
+@pytest.mark.parametrize("name", ["c128", "c64"])
+def test_every_fused_pass_compiles(Q, name):
+    dtype = Q.QS_C128 if name == "c128" else Q.QS_C64
+    n = 14
+    rng = np.random.default_rng(5)
+    lists = [
+        C.random_circuit(n, 120, rng).ops,              # U / CU, remaps, controls everywhere
+        C.qft_circuit(n).ops,                          # phase runs with tables
+        C.iqft_circuit(n).ops,
+    ]
+    for ops in lists:
+        nk = Q.qs_precompile(n, dtype, ops)
+        assert nk == _plan_fused(Q, n, dtype, ops) and nk > 0
+
+
+def test_adjoint_passes_compile_and_cache_by_shape(Q):
+    n = 13
+    circ, _ = C.workload_ansatz(n, 3, 5, seed=11)
+    before = Q.qs_get_jit_stats()
+    nk = Q.qs_precompile(n, Q.QS_C128, circ.ops, circ.theta, Q.QS_PRECOMPILE_ADJOINT)
+    mid = Q.qs_get_jit_stats()
+    assert nk > 0 and mid["kernels_compiled"] >= before["kernels_compiled"]
+    # new angles, same circuit form: every kernel is already cached
+    theta2 = np.random.default_rng(3).uniform(0, 2 * np.pi, circ.nparams)
+    assert Q.qs_precompile(n, Q.QS_C128, circ.ops, theta2, Q.QS_PRECOMPILE_ADJOINT) == nk
+    after = Q.qs_get_jit_stats()
+    assert after["kernels_compiled"] == mid["kernels_compiled"]
+    assert after["kernels_cached"] >= nk and after["compile_seconds"] > 0.0
+
+
+def test_precompile_validates_its_arguments(Q):
+    ops = C.random_circuit(12, 10, np.random.default_rng(1)).ops
+    with pytest.raises(Q.QSError):
+        Q.qs_precompile(12, 7, ops)
+    with pytest.raises(Q.QSError):
+        Q.qs_precompile(40, Q.QS_C128, ops)
+    with pytest.raises(Q.QSError):
+        Q.qs_precompile(12, Q.QS_C128, ops, flags=8)
+    bad = ops.copy()
+    bad[0]["target"] = 12
+    with pytest.raises(Q.QSError):
+        Q.qs_precompile(12, Q.QS_C128, bad)
