@@ -706,8 +706,6 @@ static FusedArgs pass_args(const StateImpl* s, const Plan& plan, const Pass& p, 
   return A;
 }
 
-static int device_cus(StateImpl* s);
-
 bool use_compiled_passes(const StateImpl* s) {
   if (s->exec == QS_EXEC_COMPILED) return true;
   if (s->exec == QS_EXEC_INTERPRETED) return false;
@@ -781,15 +779,12 @@ Status run_gates(StateImpl* s, const std::vector<XGate>& gates, int flags) {
       bool runs = false;
       for (int i = p.op_first; i < p.op_first + p.nops; ++i) runs |= plan.ops[i].kind == kOpPhaseRun;
       if (!jp.empty() && jp[pi].entry >= 0) {
-        unsigned g = grid;
-        if (jp[pi].persistent)
-          g = (unsigned)std::min<uint64_t>(g, (uint64_t)device_cus(s) * jit_pipe_wg_per_cu());
         void* a = s->ptr;
         const FOp* o = dops + p.op_first;
         const void* mp = dmaps;
         unsigned long long nt = A.ntiles;
         void* args[] = {&a, &o, &mp, &nt};
-        st = launch_compiled(s, jp[pi], g, args);
+        st = launch_compiled(s, jp[pi], grid, args);
         if (!st.good()) return st;
         continue;
       }

@@ -230,9 +230,7 @@ bool gate_is_diagonal(const XGate& g);
 // their text.  entry < 0: the pass runs on the interpreter kernels.
 struct JitPass {
   int entry = -1;
-  bool persistent = false;  // a software-pipelined loop over tiles: launch a resident grid
 };
-int jit_pipe_wg_per_cu();
 struct JitStats {
   long long kernels = 0;         // kernels compiled by this process
   long long cached = 0;          // kernels held in the cache

@@ -127,8 +127,8 @@ int regoff(const Geo& g, const FMap& m, int r) {
 
 class PassEmitter {
  public:
-  PassEmitter(const Plan& plan, const Pass& p, int n, int dtype, bool adj, bool pipe)
-      : plan_(plan), p_(p), n_(n), adj_(adj), pipe_(pipe && !adj) {
+  PassEmitter(const Plan& plan, const Pass& p, int n, int dtype, bool adj)
+      : plan_(plan), p_(p), n_(n), adj_(adj) {
     const FuseGeom G = fuse_geom(dtype);
     g_.dtype = dtype;
     g_.nreg = G.nreg;
@@ -153,7 +153,6 @@ class PassEmitter {
   const Pass& p_;
   int n_;
   bool adj_;
-  bool pipe_;  // software-pipelined tile loop (forward passes)
   Geo g_;
   Src src_;
   std::vector<int> thr_off_emitted_;
@@ -240,10 +239,10 @@ class PassEmitter {
     return name;
   }
 
-  void emit_load(const char* XR, const char* XI, const char* ptr, const char* basev = "base") {
+  void emit_load(const char* XR, const char* XI, const char* ptr) {
     const FMap& m = plan_.maps[p_.map_load];
     src_("    {");
-    src_("      const unsigned long long ub = %s | %s;", basev, wave_part(m).c_str());
+    src_("      const unsigned long long ub = base | %s;", wave_part(m).c_str());
     if (!g_.c64) {
       src_("      const qs_d2* pa = %s + ub;", ptr);
       for (int r = 0; r < g_.RA; ++r) {
@@ -333,10 +332,16 @@ class PassEmitter {
     snprintf(b, sizeof b, "op%d_", i - p_.op_first);
     return b;
   }
+  // Only the offset goes through the asm: the pointer stays derived from
+  // the kernel's restrict, read-only `ops`, so its records are still read
+  // with scalar loads (an opaque pointer would be read with vector loads
+  // that queue behind the tile's).
   void release_op(int i) {
     if (i >= p_.op_first + p_.nops) return;
-    src_("    const QsOp* %s = ops + %d;", opref(i).c_str(), i - p_.op_first);
-    src_("    asm volatile(\"\" : \"+s\"(%s));", opref(i).c_str());
+    const std::string r = opref(i);
+    src_("    int %so = %d;", r.c_str(), i - p_.op_first);
+    src_("    asm volatile(\"\" : \"+s\"(%so));", r.c_str());
+    src_("    const QsOp* %s = ops + %so;", r.c_str(), r.c_str());
   }
 
   void emit_u(int i) {
@@ -536,14 +541,6 @@ class PassEmitter {
     }
     src_("  R xr[%d], xi[%d];", g_.RA, g_.RA);
     if (adj_) src_("  R yr[%d], yi[%d];", g_.RA, g_.RA);
-    if (pipe_) {
-      // the next tile's amplitudes are loaded while this one is computed
-      src_("  R nr[%d], ni[%d];", g_.RA, g_.RA);
-      src_("  if ((unsigned long long)blockIdx.x < ntiles) {");
-      emit_base("nbase", "(unsigned long long)blockIdx.x");
-      emit_load("nr", "ni", "qa", "nbase");
-      src_("  }");
-    }
     src_("  for (unsigned long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {");
     emit_base("base", "tile");
     // per-thread phase-run tables: read before this iteration's tile loads
@@ -558,15 +555,7 @@ class PassEmitter {
       }
       i += op.aux;
     }
-    if (pipe_) {
-      for (int r = 0; r < g_.RA; ++r) src_("    xr[%d] = nr[%d]; xi[%d] = ni[%d];", r, r, r, r);
-      src_("    if (tile + gridDim.x < ntiles) {");
-      emit_base("nbase", "(tile + gridDim.x)");
-      emit_load("nr", "ni", "qa", "nbase");
-      src_("    }");
-    } else {
-      emit_load("xr", "xi", "qa");
-    }
+    emit_load("xr", "xi", "qa");
     if (adj_) emit_load("yr", "yi", "ql");
     // op records: op i's pointer is released at the start of op i - 1
     int released = p_.op_first;
@@ -635,17 +624,6 @@ std::vector<JitEntry> g_entries;
 std::vector<JitProgram> g_programs;
 JitStats g_stats;
 
-// Optional occupancy target for generated kernels (QS_JIT_WAVES=<waves per
-// SIMD>), part of every cache key through the kernel text.
-std::string jit_kernel_attrs() {
-  const char* e = getenv("QS_JIT_WAVES");
-  const int w = e ? atoi(e) : 0;
-  if (w <= 0) return std::string();
-  char b[64];
-  snprintf(b, sizeof b, "__attribute__((amdgpu_waves_per_eu(%d))) ", w);
-  return b;
-}
-
 uint64_t fnv1a(const std::string& s) {
   uint64_t h = 1469598103934665603ull;
   for (unsigned char c : s) {
@@ -666,7 +644,6 @@ void compile_job(CompileJob* job) {
   std::string src = kPrelude;
   for (auto& k : job->kernels) {
     src += "extern \"C\" __global__ void __launch_bounds__(256) ";
-    src += jit_kernel_attrs();
     src += k.first;
     src += k.second;
   }
@@ -784,23 +761,9 @@ Status function_on(int entry, int dev, hipFunction_t* out) {
 
 }  // namespace
 
-bool jit_pipelined(bool adjoint) {
-  if (adjoint) return false;
-  const char* e = getenv("QS_JIT_PIPE");
-  return e && atoi(e) > 0;
-}
-
-int jit_pipe_wg_per_cu() {
-  const char* e = getenv("QS_JIT_PIPE_WG");
-  const int v = e ? atoi(e) : 0;
-  return v > 0 ? v : 4;
-}
-
 std::string jit_pass_text(const Plan& plan, const Pass& p, int n, int dtype, bool adjoint) {
-  PassEmitter em(plan, p, n, dtype, adjoint, jit_pipelined(adjoint));
-  std::string b = em.body();
-  if (b.empty()) return b;
-  return "/*" + jit_kernel_attrs() + "*/" + b;
+  PassEmitter em(plan, p, n, dtype, adjoint);
+  return em.body();
 }
 
 Status jit_prepare(const Plan& plan, int n, int dtype, bool adjoint, std::vector<JitPass>* out) {
@@ -817,10 +780,7 @@ Status jit_prepare(const Plan& plan, int n, int dtype, bool adjoint, std::vector
   std::vector<int> idx;
   Status st = ensure_compiled(texts, &idx);
   if (!st.good()) return st;
-  for (size_t j = 0; j < which.size(); ++j) {
-    (*out)[(size_t)which[j]].entry = idx[j];
-    (*out)[(size_t)which[j]].persistent = jit_pipelined(adjoint);
-  }
+  for (size_t j = 0; j < which.size(); ++j) (*out)[(size_t)which[j]].entry = idx[j];
   return Status::ok();
 }
 
