@@ -64,7 +64,61 @@ def parse():
     ap.add_argument("--ps-pairs", type=int, default=8,
                     help="parameter-shift pairs timed at n=28 (extrapolated to all 2P sweeps)")
     ap.add_argument("--cpu-n", type=int, default=0, help="qubits of the CPU-oracle sample (0 = auto)")
+    ap.add_argument("--workload-only", choices=["circuit", "qft", "iqft", "adjoint", "batch"],
+                    help="run one workload once after a warmup, plus a 4 GiB STREAM copy, and exit "
+                         "(for hardware-counter runs): the 1000-gate random circuit, the QFT or IQFT on "
+                         "all qubits at --n/--dtype, the n = 28 ansatz energy + gradient (--dtype), or "
+                         "the 4096-circuit batch (--dtype)")
     return ap.parse_args()
+
+
+def workload_only(args) -> None:
+    """One workload, once, after an untimed warmup (which compiles the pass
+    kernels), then the STREAM copy used to calibrate the traffic counters."""
+    import numpy as np
+    import torch
+
+    import circuits as C
+    import paper_1601_07195_amd.qs as Q
+
+    torch.cuda.set_device(0)
+    dtype = Q.QS_C128 if args.dtype == "c128" else Q.QS_C64
+    w = args.workload_only
+    if w in ("circuit", "qft", "iqft"):
+        n = args.n
+        ops = {"circuit": lambda: C.random_circuit(n, args.circuit_gates, np.random.default_rng(C.SEED_BASE + 1)),
+               "qft": lambda: C.qft_circuit(n), "iqft": lambda: C.iqft_circuit(n)}[w]().ops
+        st = Q.State(n, dtype)
+        st.run(ops)
+        torch.cuda.synchronize()
+        log(f"[bench] {w} n={n} {args.dtype}: warmup done")
+        st.run(ops)
+        torch.cuda.synchronize()
+        del st
+    elif w == "adjoint":
+        n = 28
+        circ, ham = C.workload_ansatz(n, 20, 100)
+        st = Q.State(n, dtype)
+        lam = Q.State(n, dtype, init=False)
+        for _ in range(2):
+            st.init_basis(0)
+            Q.grad_adjoint(st, lam, circ.ops, circ.theta, ham.codes, ham.coeff)
+            torch.cuda.synchronize()
+        del st, lam
+    else:
+        wl = C.workload_batch(4096)
+        b = Q.Batch([(c.n, c.ops, c.theta, h.codes, h.coeff) for c, h in wl], dtype)
+        b.run_flat()
+        b.run_flat()
+        torch.cuda.synchronize()
+        b.close()
+    torch.cuda.empty_cache()
+    cs = 4 << 30
+    src = torch.empty(cs // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    Q.qs_stream_copy(src, dst)
+    torch.cuda.synchronize()
+    log(f"[bench] workload {w} done")
 
 
 def log(msg: str) -> None:
@@ -111,9 +165,10 @@ def measured_traffic(kernel: str, workload: str):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip().strip("`")
     try:
-        src = os.path.join(ROOT, fields["source_file"])
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if sha != fields["source_sha256"]:
+        h = hashlib.sha256()
+        for f in fields["source_file"].split(","):
+            h.update(open(os.path.join(ROOT, f.strip()), "rb").read())
+        if h.hexdigest() != fields["source_sha256"]:
             return None
         return float(fields["traffic_bytes_per_launch"])
     except (KeyError, OSError, ValueError):
@@ -166,13 +221,84 @@ def cpu_baseline(n_gpu: int, u, pairs, args):
     nbytes, dt = run(gates)
     O.set_threads(1)
     nb1, dt1 = run([("1q", 0, C.H_GATE), ("1q", n - 1, C.H_GATE)])
-    return {
+    del psi
+    out = {
         "value": round(nbytes / dt / 1e9, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
         "sample": f"complex128 n={n}: H and Haar U on all {n} targets + {len(gates) - 2 * n} "
                   f"controlled-U, {len(gates)} gates, {dt:.2f} s",
         "one_core_GBps": round(nb1 / dt1 / 1e9, 3),
         "one_core_sample": f"H on targets 0 and {n - 1}, {dt1:.2f} s",
     }
+    out.update(host_info(threads))
+    out["host_stream_copy_GBps"] = host_stream_copy(np, threads)
+    out["oracle_vs_host_copy"] = round(out["value"] / out["host_stream_copy_GBps"], 3)
+    out["workloads"] = oracle_workloads(np, C, O, threads)
+    return out
+
+
+def host_info(threads: int) -> dict:
+    """The host the oracle ran on: logical CPUs, the CPU model, and the share
+    used (the GPU machine grants 16 threads per GPU whatever the CPU count)."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model, "threads_used": threads,
+            "threads_note": "oracle threads capped at the 16-thread CPU share of one GPU"}
+
+
+def host_stream_copy(np, threads: int) -> float:
+    """Host STREAM-copy bandwidth (the paper's B_mem definition, Sec. 5.2):
+    a 4 GiB float64 copy split over the oracle's threads (numpy releases the
+    GIL while copying), best of three, counted as read + write bytes."""
+    import concurrent.futures as cf
+    a = np.ones((1 << 29,), dtype=np.float64)
+    b = np.empty_like(a)
+    parts = np.array_split(np.arange(a.size), threads)
+    spans = [(int(p[0]), int(p[-1]) + 1) for p in parts if p.size]
+    best = 0.0
+    with cf.ThreadPoolExecutor(threads) as ex:
+        list(ex.map(lambda r: np.copyto(b[r[0]:r[1]], a[r[0]:r[1]]), spans))
+        for _ in range(3):
+            t0 = time.perf_counter()
+            list(ex.map(lambda r: np.copyto(b[r[0]:r[1]], a[r[0]:r[1]]), spans))
+            best = max(best, 2 * a.nbytes / (time.perf_counter() - t0) / 1e9)
+    del a, b
+    return round(best, 2)
+
+
+def oracle_workloads(np, C, O, threads: int) -> dict:
+    """The oracle on the small workloads in full: the 200-gate n = 20 circuit
+    with its probabilities, and the n = 20 ansatz energy; at n = 28 the
+    ansatz's parameter shift extrapolated from ten timed gates (labelled)."""
+    out = {}
+    O.set_threads(threads)
+    circ = C.workload_gates(20, 200)
+    t0 = time.perf_counter()
+    psi = O.run(circ.ops, 20)
+    O.probabilities(psi, 20)
+    out["n20_200_gates_and_probabilities_s"] = round(time.perf_counter() - t0, 3)
+    ac, ham = C.workload_ansatz(20, 20, 100)
+    t0 = time.perf_counter()
+    O.energy(ac.ops, 20, ac.theta, ham.codes, ham.coeff)
+    t_e20 = time.perf_counter() - t0
+    out["n20_ansatz_energy_s"] = round(t_e20, 3)
+    out["n20_ansatz_param_shift_s_extrapolated"] = round(2 * ac.nparams * t_e20, 1)
+    a28, h28 = C.workload_ansatz(28, 20, 100)
+    psi = O.basis_state(28)
+    t0 = time.perf_counter()
+    O.run(a28.ops[:10], 28, a28.theta, psi=psi)
+    per_gate = (time.perf_counter() - t0) / 10
+    t_e28 = per_gate * len(a28.ops)
+    out["n28_ansatz_energy_s_extrapolated"] = round(t_e28, 1)
+    out["n28_ansatz_param_shift_s_extrapolated"] = round(2 * a28.nparams * t_e28, 0)
+    out["note"] = "extrapolated entries: time of 10 gates (n = 28) or one energy (n = 20) times the gate or sweep count"
+    del psi
+    return out
 
 
 def timed(fn, stream, reps=1):
@@ -391,7 +517,7 @@ def adjoint_section(Q, C, np, torch, ps_pairs):
             gps[j] = 0.5 * (energy(tp) - energy(tm))
         t_pairs = time.perf_counter() - t0
         t_ps = t_pairs * P / pairs
-        out[f"n{n}"] = {
+        rec = {
             "params": P, "gates": len(circ), "terms": 100,
             "adjoint_s": round(t_adj, 4), "param_shift_s": round(t_ps, 3),
             "param_shift_pairs_timed": pairs,
@@ -402,6 +528,43 @@ def adjoint_section(Q, C, np, torch, ps_pairs):
         }
         del st, lam
         torch.cuda.empty_cache()
+        # the same energy and gradient on a complex64 state (FP64 accumulation)
+        s64 = Q.State(n, Q.QS_C64, stream=stream)
+        l64 = Q.State(n, Q.QS_C64, stream=stream, init=False)
+
+        def adj64():
+            s64.init_basis(0)
+            return Q.qs_grad_adjoint(s64.handle, circ.ops, circ.theta, x, z, ham.coeff, l64.handle)
+
+        adj64()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            e64, g64 = adj64()
+        rec["c64_adjoint_s"] = round((time.perf_counter() - t0) / reps, 4)
+        rec["c64_max_abs_diff_vs_c128"] = {"energy": abs(e64 - e), "gradient": float(np.abs(g64 - g).max())}
+        del s64, l64
+        torch.cuda.empty_cache()
+        if n == 20:
+            rec["error_vs_fp64_oracle"] = oracle_errors(C, np, circ, ham, n, {"c128": (e, g), "c64": (e64, g64)})
+        out[f"n{n}"] = rec
+    return out
+
+
+def oracle_errors(C, np, circ, ham, n, results, nsample=8):
+    """Energy and sampled-gradient errors of GPU results against the FP64
+    CPU oracle (its energy, and its parameter-shift rule on `nsample`
+    parameters spread over the circuit, first and last included)."""
+    import oracle as O
+    O.set_threads(min(16, os.cpu_count() or 1))
+    P = circ.nparams
+    params = sorted({int(round(j * (P - 1) / (nsample - 1))) for j in range(nsample)})
+    t0 = time.perf_counter()
+    re = O.energy(circ.ops, n, circ.theta, ham.codes, ham.coeff)
+    rg = O.grad_param_shift(circ.ops, n, circ.theta, ham.codes, ham.coeff, params=params)
+    out = {"params_checked": params, "oracle_s": round(time.perf_counter() - t0, 2)}
+    for k, (e, g) in results.items():
+        out[k] = {"energy_abs_err": abs(e - re), "gradient_max_abs_err": float(np.abs(g[params] - rg[params]).max())}
     return out
 
 
@@ -466,9 +629,40 @@ def batch_section(Q, C, np, torch):
         else:
             rec["max_abs_diff_vs_c128"] = {"energy": float(np.abs(e - ref[0]).max()),
                                            "gradient": float(np.abs(g - ref[1]).max())}
+        rec["error_vs_fp64_oracle"] = batch_oracle_errors(C, np, items, e, g)
         out[name] = rec
         b.close()
     return out
+
+
+def batch_oracle_errors(C, np, items, e, g, nsample=8):
+    """Errors of batched results against the FP64 CPU oracle on a seeded
+    sample of circuits (the widest-deepest and the deepest among them):
+    energies, and the parameter-shift gradient on six parameters each."""
+    import oracle as O
+    O.set_threads(min(16, os.cpu_count() or 1))
+    ns = np.array([it[0] for it in items])
+    depth = np.array([len(it[1]) for it in items])
+    pick = [int(np.argmax(depth + (ns == ns.max()) * 10 ** 6)), int(np.argmax(depth))]
+    for i in np.random.default_rng(4096).choice(len(items), nsample, replace=False):
+        if int(i) not in pick:
+            pick.append(int(i))
+    pick = pick[:nsample]
+    off = np.concatenate([[0], np.cumsum([len(it[2]) for it in items])])
+    worst_e = worst_g = 0.0
+    t0 = time.perf_counter()
+    for i in pick:
+        n, ops, th, codes, coeff = items[i]
+        P = len(th)
+        params = sorted({0, 1, n, P // 2, P - n - 1, P - 1})
+        re = O.energy(ops, n, th, codes, coeff)
+        rg = O.grad_param_shift(ops, n, th, codes, coeff, params=params)
+        gi = np.asarray(g[off[i]:off[i + 1]])
+        worst_e = max(worst_e, abs(float(e[i]) - re))
+        worst_g = max(worst_g, float(np.abs(gi[params] - rg[params]).max()))
+    return {"circuits": pick, "qubits": [int(items[i][0]) for i in pick],
+            "energy_max_abs_err": worst_e, "gradient_max_abs_err": worst_g,
+            "oracle_s": round(time.perf_counter() - t0, 2)}
 
 
 def main():
@@ -477,6 +671,9 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               f"(the simulator holds the whole state on one GPU).", file=sys.stderr)
         sys.exit(2)
+    if args.workload_only:
+        workload_only(args)
+        return
 
     import numpy as np
     import torch
@@ -608,7 +805,7 @@ def main():
     dom = max(kernels, key=lambda k: kernels[k]["step_s"])
     traffic = None
     if dom.startswith("k_fused"):
-        traffic = measured_traffic(f"k_fused_{args.dtype}", f"n{n}")
+        traffic = measured_traffic(f"qs_pass_compiled_circuit_{args.dtype}", f"n{n}")
     roof = {"kernel": dom, "bound": "hbm", "achieved": kernels[dom]["achieved_GBps"],
             "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": kernels[dom]["frac"], "traffic": traffic,
             "bytes_per_launch": kernels[dom]["bytes_per_launch"],
@@ -673,7 +870,71 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle sample")
         line["cpu_baseline"] = cpu_baseline(n, u, pairs, args)
+    js = Q.qs_get_jit_stats()
+    line["compiled_passes"] = {
+        "kernels_compiled": js["kernels_compiled"], "compile_s_total": round(js["compile_seconds"], 2),
+        "note": "fused passes at n >= 26 run kernels compiled per pass shape; compiled during warmup "
+                "and the untimed first call of each section, never inside a timed region"}
+    line["precision_summary"] = precision_summary(line)
+    line["per_gate_summary"] = per_gate_summary(line, n, args.dtype, S)
     print(json.dumps(line), flush=True)
+
+
+def precision_summary(line: dict) -> dict:
+    """Errors against the FP64 CPU oracle of the energy / gradient results:
+    the n = 20 ansatz (L = 20, 100 strings) and the 4096-circuit batch
+    (sampled circuits), complex128 and complex64 states."""
+    out = {}
+    a = line.get("adjoint_vs_param_shift", {}).get("n20", {}).get("error_vs_fp64_oracle")
+    if a:
+        out["ansatz_n20"] = {k: a[k] for k in ("c128", "c64") if k in a}
+    b = line.get("batch", {})
+    for k in ("c128", "c64"):
+        if k in b and "error_vs_fp64_oracle" in b[k]:
+            r = b[k]["error_vs_fp64_oracle"]
+            out.setdefault("batch_4096", {})[k] = {"energy_abs_err": r["energy_max_abs_err"],
+                                                  "gradient_max_abs_err": r["gradient_max_abs_err"]}
+    return out
+
+
+def per_gate_summary(line: dict, n: int, dtype: str, S: int) -> dict:
+    """The figures the per-gate HBM claim rests on, for n = 30, 33 and 34,
+    gathered from the sections above (GB/s of algorithmic bytes, and the
+    fraction of the 8 TB/s peak)."""
+    def frac(v):
+        return None if v is None else round(v / PEAK_HBM_GBPS, 3)
+    d = line["detail"]
+    one = list(d["one_qubit_GBps_by_target"].values())
+    out = {f"n{n}_{dtype}": {
+        "one_qubit_min_GBps": round(min(one), 1), "one_qubit_median_GBps": round(statistics.median(one), 1),
+        "cu_control_outside_line_GBps": d["cu_GBps_control_outside_line"],
+        "cu_control_inside_line_GBps": d["cu_GBps_control_inside_line"],
+        "fused_circuit_hbm_GBps": d["circuit_hbm_GBps"],
+        "fused_pass_frac": line["roofline"]["frac"],
+    }}
+    q = line.get("qft_fused_vs_unfused", {}).get("c128", {}).get(str(n))
+    if q:
+        out[f"n{n}_{dtype}"]["qft_fused_hbm_GBps"] = q["qft"]["fused_hbm_GBps"]
+        out[f"n{n}_{dtype}"]["iqft_fused_hbm_GBps"] = q["iqft"]["fused_hbm_GBps"]
+    for key, rec in line.get("large_states", {}).items():
+        lb = 3 if key.endswith("c128") else 4
+        cu_in = [v for k, v in rec["cu_alg_GBps"].items() if int(k.split(",")[0]) < lb]
+        cu_out = [v for k, v in rec["cu_alg_GBps"].items() if int(k.split(",")[0]) >= lb]
+        o1 = list(rec["one_qubit_GBps_by_target"].values())
+        qo = rec["qft_only"]
+        Sx = rec["state_bytes"]
+        out[key] = {
+            "one_qubit_min_GBps": round(min(o1), 1), "one_qubit_median_GBps": round(statistics.median(o1), 1),
+            "cu_control_outside_line_GBps": round(statistics.fmean(cu_out), 1) if cu_out else None,
+            "cu_control_inside_line_GBps": round(statistics.fmean(cu_in), 1) if cu_in else None,
+            "fused_circuit_hbm_GBps": rec["circuit"]["hbm_GBps"],
+            "qft_per_pass_hbm_GBps": round(qo["passes"] * 2 * Sx / qo["s"] / 1e9, 1),
+        }
+    for v in out.values():
+        for k in list(v):
+            if k.endswith("_GBps"):
+                v[k.replace("_GBps", "_frac")] = frac(v[k])
+    return out
 
 
 if __name__ == "__main__":

@@ -170,12 +170,16 @@ int qs_set_fused_exec(qs_state* s, int mode);
 int qs_precompile(int n, int dtype, const qs_op* ops, int nops, const double* theta,
                   int nparams, int flags, int32_t* nkernels);
 
-/* Counters of the compiled-pass cache of this process. */
+/* Counters of the compiled-pass cache of this process.  With the
+ * environment variable QS_JIT_CACHE_DIR naming a writable directory,
+ * compiled kernels are also kept there and loaded by later processes
+ * (each kernel's text is stored beside it and compared in full). */
 typedef struct qs_jit_stats {
   int64_t kernels_compiled;  /* kernels compiled so far */
   int64_t kernels_cached;    /* kernels held in the cache */
   int64_t modules_loaded;    /* code objects loaded onto devices */
   double compile_seconds;    /* host wall time spent compiling */
+  int64_t kernels_from_disk; /* kernels loaded from the on-disk cache */
 } qs_jit_stats;
 int qs_get_jit_stats(qs_jit_stats* out);
 

@@ -346,6 +346,7 @@ int qs_get_jit_stats(qs_jit_stats* out) {
   out->kernels_cached = j.cached;
   out->modules_loaded = j.modules_loaded;
   out->compile_seconds = j.compile_seconds;
+  out->kernels_from_disk = j.loaded_from_disk;
   return QS_OK;
 }
 

@@ -236,6 +236,7 @@ struct JitStats {
   long long cached = 0;          // kernels held in the cache
   long long modules_loaded = 0;  // code objects loaded on a device
   double compile_seconds = 0.0;  // wall time spent compiling
+  long long loaded_from_disk = 0;  // kernels found in the on-disk cache
 };
 // Kernel text of one fused pass (after the kernel's name); empty when the
 // generator does not take the pass.

@@ -27,7 +27,10 @@
 #include <algorithm>
 #include <chrono>
 #include <fstream>
+#include <cstdio>
+#include <functional>
 #include <mutex>
+#include <sstream>
 #include <string>
 #include <thread>
 #include <unordered_map>
@@ -611,6 +614,7 @@ class PassEmitter {
 struct JitProgram {
   std::string code;                  // code object
   std::vector<hipModule_t> modules;  // per device (null until loaded)
+  std::string file;                  // its file in the on-disk cache, when loaded from there
 };
 struct JitEntry {
   int program = -1;
@@ -682,6 +686,42 @@ void compile_job(CompileJob* job) {
   job->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
+// ------------------------------------------------------- on-disk cache
+// With QS_JIT_CACHE_DIR set, every compiled program is also written there
+// (p_<hash>.co) with, per kernel, its text (k_<hash>.txt, compared in full on
+// lookup) and the program that holds it (k_<hash>.prog), so that other
+// processes load instead of compiling.
+std::string cache_dir() {
+  const char* e = getenv("QS_JIT_CACHE_DIR");
+  return e ? std::string(e) : std::string();
+}
+
+bool read_file(const std::string& path, std::string* out) {
+  std::ifstream f(path, std::ios::binary);
+  if (!f) return false;
+  std::ostringstream ss;
+  ss << f.rdbuf();
+  *out = ss.str();
+  return true;
+}
+
+void write_file(const std::string& path, const std::string& data) {
+  const std::string tmp = path + ".tmp" + std::to_string((unsigned long long)std::hash<std::thread::id>()(std::this_thread::get_id()));
+  {
+    std::ofstream f(tmp, std::ios::binary);
+    if (!f) return;
+    f.write(data.data(), (std::streamsize)data.size());
+    if (!f) return;
+  }
+  std::rename(tmp.c_str(), path.c_str());
+}
+
+std::string hex64(uint64_t h) {
+  char b[20];
+  snprintf(b, sizeof b, "%016llx", (unsigned long long)h);
+  return b;
+}
+
 int compile_threads() {
   const char* e = getenv("QS_JIT_THREADS");
   int t = e ? atoi(e) : 0;
@@ -699,6 +739,35 @@ Status ensure_compiled(const std::vector<std::string>& texts, std::vector<int>* 
       if (!g_index.count(t) && std::find(missing.begin(), missing.end(), t) == missing.end())
         missing.push_back(t);
   }
+  const std::string dir = cache_dir();
+  if (!dir.empty() && !missing.empty()) {
+    // kernels another process compiled: load their programs
+    std::vector<std::string> still;
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (const std::string& t : missing) {
+      const std::string h = hex64(fnv1a(t));
+      std::string txt, prog, code;
+      if (!read_file(dir + "/k_" + h + ".txt", &txt) || txt != t || !read_file(dir + "/k_" + h + ".prog", &prog) ||
+          !read_file(dir + "/" + prog, &code) || code.empty()) {
+        still.push_back(t);
+        continue;
+      }
+      int pi = -1;
+      for (size_t i = 0; i < g_programs.size(); ++i)
+        if (g_programs[i].file == prog) pi = (int)i;
+      if (pi < 0) {
+        pi = (int)g_programs.size();
+        g_programs.push_back(JitProgram{std::move(code), {}, prog});
+      }
+      JitEntry e;
+      e.program = pi;
+      e.name = "qs_pass_" + h;
+      g_index[t] = (int)g_entries.size();
+      g_entries.push_back(std::move(e));
+      ++g_stats.loaded_from_disk;
+    }
+    missing.swap(still);
+  }
   if (!missing.empty()) {
     const auto t0 = std::chrono::steady_clock::now();
     const int nthreads = std::min<int>(compile_threads(), (int)missing.size());
@@ -714,10 +783,23 @@ Status ensure_compiled(const std::vector<std::string>& texts, std::vector<int>* 
     for (auto& t : th) t.join();
     for (auto& j : jobs)
       if (!j.error.empty()) return Status{QS_EHIP, "fused-pass compile failed: " + j.error};
+    if (!dir.empty()) {
+      for (auto& j : jobs) {
+        std::string all;
+        for (auto& k : j.kernels) all += k.second;
+        const std::string prog = "p_" + hex64(fnv1a(all)) + ".co";
+        write_file(dir + "/" + prog, j.code);
+        for (auto& k : j.kernels) {
+          const std::string h = hex64(fnv1a(k.second));
+          write_file(dir + "/k_" + h + ".txt", k.second);
+          write_file(dir + "/k_" + h + ".prog", prog);
+        }
+      }
+    }
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto& j : jobs) {
       const int pi = (int)g_programs.size();
-      g_programs.push_back(JitProgram{std::move(j.code), {}});
+      g_programs.push_back(JitProgram{std::move(j.code), {}, std::string()});
       for (auto& k : j.kernels) {
         if (g_index.count(k.second)) continue;
         JitEntry e;

@@ -63,3 +63,26 @@ def test_precompile_validates_its_arguments(Q):
     bad[0]["target"] = 12
     with pytest.raises(Q.QSError):
         Q.qs_precompile(12, Q.QS_C128, bad)
+
+
+def test_disk_cache_serves_a_second_process(tmp_path):
+    """With QS_JIT_CACHE_DIR set, a second process finds every kernel the
+    first compiled (its text compared in full) and compiles nothing."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys, json, numpy as np; sys.path.insert(0, %r)\n"
+            "import circuits as C, paper_1601_07195_amd.qs as Q\n"
+            "ops = C.random_circuit(13, 80, np.random.default_rng(21)).ops\n"
+            "nk = Q.qs_precompile(13, Q.QS_C64, ops)\n"
+            "print(json.dumps([nk, Q.qs_get_jit_stats()]))\n" % root)
+    env = dict(os.environ, QS_JIT_CACHE_DIR=str(tmp_path))
+    runs = [json.loads(subprocess.run([sys.executable, "-c", code], env=env, check=True,
+                                      capture_output=True, text=True).stdout.strip().splitlines()[-1])
+            for _ in range(2)]
+    (nk1, s1), (nk2, s2) = runs
+    assert nk1 == nk2 > 0
+    assert s1["kernels_compiled"] == nk1 and s1["kernels_from_disk"] == 0
+    assert s2["kernels_compiled"] == 0 and s2["kernels_from_disk"] == nk2
