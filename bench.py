@@ -337,6 +337,25 @@ def large_section(Q, C, np, torch):
         for c, t_ in [(0, 1), (2, 20), (3, 20), (10, 0), (20, 10), (n - 1, 5)] + pairs[:4]:
             t = timed(lambda: st.apply_cu(c, t_, u), stream, 3)
             cu[f"{c},{t_}"] = round(S / t / 1e9, 1)
+        # the top of the fused-vs-unfused sweep on this state: QFT and IQFT
+        # fused, and the QFT with one streaming pass per gate
+        top = {}
+        for cname, qc in (("qft", C.qft_circuit(n)), ("iqft", C.iqft_circuit(n))):
+            pg = sum((S if op["kind"] == C.OP_CU else 2 * S) for op in qc.ops)
+            qi, _, _ = Q.qs_plan(n, dtype, qc.ops)
+            tf = timed(lambda: st.run(qc.ops), stream, 1)
+            top[cname] = {"gates": len(qc), "passes_fused": qi["passes"], "fused_s": round(tf, 4),
+                          "fused_hbm_GBps": round(qi["hbm_bytes"] / tf / 1e9, 1),
+                          "fused_effective_GBps": round(pg / tf / 1e9, 1)}
+            if cname == "qft":
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st.run(qc.ops, fuse=False)
+                torch.cuda.synchronize()
+                tu = time.perf_counter() - t0
+                top[cname].update({"unfused_s": round(tu, 3), "unfused_effective_GBps": round(pg / tu / 1e9, 1),
+                                   "speedup": round(tu / tf, 1)})
+        log(f"[bench] large: n={n} {name} QFT/IQFT fused and unfused done")
         circ = C.workload_circuit_qft(n)
         info, _, _ = Q.qs_plan(n, dtype, circ.ops)
         pergate = sum((S if op["kind"] == C.OP_CU else 2 * S) for op in circ.ops)
@@ -353,6 +372,7 @@ def large_section(Q, C, np, torch):
                         "hbm_GBps": round(info["hbm_bytes"] / tc / 1e9, 1),
                         "effective_GBps_paper_def": round(pergate / tc / 1e9, 1),
                         "paper_qft_only_s": {"33": 245.0, "34": 297.4}[str(n)]},
+            "qft_iqft_fused_vs_unfused": top,
             "qft_only": {"gates": len(qft), "passes": qinfo["passes"], "s": round(tq, 4),
                          "effective_GBps_paper_def": round(
                              sum((S if op["kind"] == C.OP_CU else 2 * S) for op in qft.ops) / tq / 1e9, 1)},
@@ -370,8 +390,8 @@ def qft_section(Q, C, np, torch):
     bytes (Table 2: 2S per 1q gate, S per controlled gate) over the time."""
     out = {}
     stream = torch.cuda.current_stream()
-    for name, dtype, b, ns in (("c128", Q.QS_C128, 16, (18, 20, 22, 24, 26, 28, 30)),
-                               ("c64", Q.QS_C64, 8, (19, 21, 23, 25, 27, 29, 31))):
+    for name, dtype, b, ns in (("c128", Q.QS_C128, 16, (18, 20, 22, 24, 26, 28, 30, 31, 32)),
+                               ("c64", Q.QS_C64, 8, (19, 21, 23, 25, 27, 29, 31, 32, 33))):
         rows = {}
         for n in ns:
             S = (1 << n) * b
@@ -382,15 +402,26 @@ def qft_section(Q, C, np, torch):
                 info, _, _ = Q.qs_plan(n, dtype, circ.ops)
                 reps = 3 if n <= 24 else 1
                 tf = timed(lambda: st.run(circ.ops), stream, reps)
-                tu = timed(lambda: st.run(circ.ops, fuse=False), stream, reps)
                 rec[cname] = {
-                    "gates": len(circ), "passes_fused": info["passes"],
-                    "fused_s": round(tf, 5), "unfused_s": round(tu, 5),
+                    "gates": len(circ), "passes_fused": info["passes"], "fused_s": round(tf, 5),
                     "fused_effective_GBps": round(pergate / tf / 1e9, 1),
-                    "unfused_effective_GBps": round(pergate / tu / 1e9, 1),
                     "fused_hbm_GBps": round(info["hbm_bytes"] / tf / 1e9, 1),
-                    "speedup": round(tu / tf, 2),
                 }
+                # above 2^30 amplitudes the unfused leg (one streaming pass per
+                # gate, seconds) is timed once, for the QFT only
+                if n <= 30 or cname == "qft":
+                    if n <= 30:
+                        tu = timed(lambda: st.run(circ.ops, fuse=False), stream, reps)
+                    else:
+                        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                        e0.record(stream)
+                        st.run(circ.ops, fuse=False)
+                        e1.record(stream)
+                        e1.synchronize()
+                        tu = e0.elapsed_time(e1) * 1e-3
+                    rec[cname].update({"unfused_s": round(tu, 5),
+                                       "unfused_effective_GBps": round(pergate / tu / 1e9, 1),
+                                       "speedup": round(tu / tf, 2)})
             rows[str(n)] = rec
             del st
             torch.cuda.empty_cache()
@@ -873,6 +904,7 @@ def main():
     js = Q.qs_get_jit_stats()
     line["compiled_passes"] = {
         "kernels_compiled": js["kernels_compiled"], "compile_s_total": round(js["compile_seconds"], 2),
+        "programs_clang": js["programs_clang"], "programs_hiprtc": js["programs_hiprtc"],
         "note": "fused passes at n >= 26 run kernels compiled per pass shape; compiled during warmup "
                 "and the untimed first call of each section, never inside a timed region"}
     line["precision_summary"] = precision_summary(line)

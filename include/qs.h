@@ -170,7 +170,11 @@ int qs_set_fused_exec(qs_state* s, int mode);
 int qs_precompile(int n, int dtype, const qs_op* ops, int nops, const double* theta,
                   int nparams, int flags, int32_t* nkernels);
 
-/* Counters of the compiled-pass cache of this process.  With the
+/* Counters of the compiled-pass cache of this process.  Kernels are
+ * compiled by the ROCm clang driver ($QS_JIT_CLANG, $ROCM_PATH/llvm/bin or
+ * /opt/rocm/llvm/bin) in parallel child processes, or in-process by hipRTC
+ * when no driver is found, when a child compilation fails, or with
+ * QS_JIT_COMPILER=hiprtc (hipRTC serialises compilations).  With the
  * environment variable QS_JIT_CACHE_DIR naming a writable directory,
  * compiled kernels are also kept there and loaded by later processes
  * (each kernel's text is stored beside it and compared in full). */
@@ -180,6 +184,8 @@ typedef struct qs_jit_stats {
   int64_t modules_loaded;    /* code objects loaded onto devices */
   double compile_seconds;    /* host wall time spent compiling */
   int64_t kernels_from_disk; /* kernels loaded from the on-disk cache */
+  int64_t programs_clang;    /* compilations run by the ROCm clang driver in child processes */
+  int64_t programs_hiprtc;   /* compilations run in-process by hipRTC (the fallback) */
 } qs_jit_stats;
 int qs_get_jit_stats(qs_jit_stats* out);
 

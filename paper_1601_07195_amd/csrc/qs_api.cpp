@@ -347,6 +347,8 @@ int qs_get_jit_stats(qs_jit_stats* out) {
   out->modules_loaded = j.modules_loaded;
   out->compile_seconds = j.compile_seconds;
   out->kernels_from_disk = j.loaded_from_disk;
+  out->programs_clang = j.programs_clang;
+  out->programs_hiprtc = j.programs_hiprtc;
   return QS_OK;
 }
 

@@ -237,6 +237,8 @@ struct JitStats {
   long long modules_loaded = 0;  // code objects loaded on a device
   double compile_seconds = 0.0;  // wall time spent compiling
   long long loaded_from_disk = 0;  // kernels found in the on-disk cache
+  long long programs_clang = 0;    // programs compiled by child clang processes
+  long long programs_hiprtc = 0;   // programs compiled in-process by hipRTC
 };
 // Kernel text of one fused pass (after the kernel's name); empty when the
 // generator does not take the pass.

@@ -18,11 +18,15 @@
 // variational loop -- or the same circuit run again launches without
 // compiling.  Missing kernels of one call are compiled together, spread over
 // host threads, before the call's first launch.
+#include <fcntl.h>
 #include <hip/hiprtc.h>
+#include <spawn.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#include <sys/wait.h>
+#include <unistd.h>
 
 #include <algorithm>
 #include <chrono>
@@ -37,6 +41,8 @@
 #include <vector>
 
 #include "qs_internal.h"
+
+extern char** environ;
 
 namespace qs {
 
@@ -637,55 +643,6 @@ uint64_t fnv1a(const std::string& s) {
   return h;
 }
 
-struct CompileJob {
-  std::vector<std::pair<std::string, std::string>> kernels;  // (name, text)
-  std::string code, error;
-  double seconds = 0.0;
-};
-
-void compile_job(CompileJob* job) {
-  const auto t0 = std::chrono::steady_clock::now();
-  std::string src = kPrelude;
-  for (auto& k : job->kernels) {
-    src += "extern \"C\" __global__ void __launch_bounds__(256) ";
-    src += k.first;
-    src += k.second;
-  }
-  const char* dump = getenv("QS_JIT_DUMP");
-  if (dump && *dump) {
-    std::ofstream(std::string(dump) + "/" + job->kernels[0].first + ".hip") << src;
-  }
-  hiprtcProgram prog;
-  hiprtcResult r = hiprtcCreateProgram(&prog, src.c_str(), "qs_pass.hip", 0, nullptr, nullptr);
-  if (r != HIPRTC_SUCCESS) {
-    job->error = std::string("hiprtcCreateProgram: ") + hiprtcGetErrorString(r);
-    return;
-  }
-  const char* opts[] = {"--offload-arch=gfx950", "-O3", "-ffp-contract=fast", "-Xclang", "-target-feature",
-                        "-Xclang", "-packed-fp32-ops"};
-  r = hiprtcCompileProgram(prog, (int)(sizeof opts / sizeof opts[0]), opts);
-  if (r != HIPRTC_SUCCESS) {
-    size_t n = 0;
-    hiprtcGetProgramLogSize(prog, &n);
-    std::string log(n, '\0');
-    if (n) hiprtcGetProgramLog(prog, &log[0]);
-    if (log.size() > 2000) log.resize(2000);
-    job->error = std::string("hiprtcCompileProgram: ") + hiprtcGetErrorString(r) + "\n" + log;
-    hiprtcDestroyProgram(&prog);
-    return;
-  }
-  size_t sz = 0;
-  hiprtcGetCodeSize(prog, &sz);
-  job->code.resize(sz);
-  hiprtcGetCode(prog, &job->code[0]);
-  hiprtcDestroyProgram(&prog);
-  if (dump && *dump) {
-    std::ofstream(std::string(dump) + "/" + job->kernels[0].first + ".co", std::ios::binary)
-        .write(job->code.data(), (std::streamsize)job->code.size());
-  }
-  job->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-}
-
 // ------------------------------------------------------- on-disk cache
 // With QS_JIT_CACHE_DIR set, every compiled program is also written there
 // (p_<hash>.co) with, per kernel, its text (k_<hash>.txt, compared in full on
@@ -720,6 +677,133 @@ std::string hex64(uint64_t h) {
   char b[20];
   snprintf(b, sizeof b, "%016llx", (unsigned long long)h);
   return b;
+}
+
+struct CompileJob {
+  std::vector<std::pair<std::string, std::string>> kernels;  // (name, text)
+  std::string code, error;
+  double seconds = 0.0;
+  bool by_clang = false;  // compiled in a child clang process (else hipRTC)
+};
+
+// The ROCm clang driver, for compiling in child processes (hipRTC
+// serialises compilations inside one process); empty when not found or
+// when QS_JIT_COMPILER=hiprtc.
+std::string clang_path() {
+  const char* mode = getenv("QS_JIT_COMPILER");
+  if (mode && !strcmp(mode, "hiprtc")) return std::string();
+  std::vector<std::string> cands;
+  if (const char* e = getenv("QS_JIT_CLANG")) cands.push_back(e);
+  if (const char* r = getenv("ROCM_PATH")) cands.push_back(std::string(r) + "/llvm/bin/clang++");
+  cands.push_back("/opt/rocm/llvm/bin/clang++");
+  for (const std::string& c : cands)
+    if (!c.empty() && access(c.c_str(), X_OK) == 0) return c;
+  return std::string();
+}
+
+// Compile `src` with the clang driver in a child process into a code
+// object; false (with job->error set) if anything fails.
+bool compile_with_clang(const std::string& clang, const std::string& src, CompileJob* job) {
+  const char* td = getenv("TMPDIR");
+  std::string dir = std::string(td && *td ? td : "/tmp") + "/qsjitXXXXXX";
+  if (!mkdtemp(&dir[0])) {
+    job->error = "mkdtemp failed";
+    return false;
+  }
+  const std::string in = dir + "/pass.hip", out = dir + "/pass.hsaco";
+  {
+    std::ofstream f(in, std::ios::binary);
+    f << src;
+    if (!f) {
+      job->error = "cannot write " + in;
+      rmdir(dir.c_str());
+      return false;
+    }
+  }
+  std::string rocm = clang.substr(0, clang.rfind("/llvm/bin/"));
+  const std::string rocm_arg = "--rocm-path=" + (rocm.empty() ? std::string("/opt/rocm") : rocm);
+  std::vector<std::string> args = {clang, "-x", "hip", "-std=c++17", "--offload-arch=gfx950", "--cuda-device-only",
+                                   "--no-gpu-bundle-output", "-O3", "-ffp-contract=fast", "-Xclang",
+                                   "-target-feature", "-Xclang", "-packed-fp32-ops", rocm_arg, "-include",
+                                   "hip/hip_runtime.h", "-w", in, "-o", out};
+  std::vector<char*> argv;
+  for (auto& a : args) argv.push_back(&a[0]);
+  argv.push_back(nullptr);
+  posix_spawn_file_actions_t fa;
+  posix_spawn_file_actions_init(&fa);
+  const std::string log = dir + "/log.txt";
+  posix_spawn_file_actions_addopen(&fa, 1, log.c_str(), O_WRONLY | O_CREAT | O_TRUNC, 0600);
+  posix_spawn_file_actions_adddup2(&fa, 1, 2);
+  pid_t pid = 0;
+  const int rc = posix_spawn(&pid, clang.c_str(), &fa, nullptr, argv.data(), environ);
+  posix_spawn_file_actions_destroy(&fa);
+  int status = 0;
+  bool ok = rc == 0 && waitpid(pid, &status, 0) == pid && WIFEXITED(status) && WEXITSTATUS(status) == 0 &&
+            read_file(out, &job->code) && !job->code.empty();
+  if (!ok) {
+    std::string msg;
+    read_file(log, &msg);
+    if (msg.size() > 2000) msg.resize(2000);
+    job->error = "clang (" + clang + ") failed: " + msg;
+    job->code.clear();
+  }
+  unlink(in.c_str());
+  unlink(out.c_str());
+  unlink(log.c_str());
+  rmdir(dir.c_str());
+  return ok;
+}
+
+void compile_job(CompileJob* job) {
+  const auto t0 = std::chrono::steady_clock::now();
+  std::string src = kPrelude;
+  for (auto& k : job->kernels) {
+    src += "extern \"C\" __global__ void __launch_bounds__(256) ";
+    src += k.first;
+    src += k.second;
+  }
+  const char* dump = getenv("QS_JIT_DUMP");
+  if (dump && *dump) {
+    std::ofstream(std::string(dump) + "/" + job->kernels[0].first + ".hip") << src;
+  }
+  const std::string clang = clang_path();
+  if (!clang.empty()) {
+    if (compile_with_clang(clang, src, job)) {
+      job->by_clang = true;
+      job->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      return;
+    }
+    job->error.clear();  // fall back to hipRTC
+  }
+  hiprtcProgram prog;
+  hiprtcResult r = hiprtcCreateProgram(&prog, src.c_str(), "qs_pass.hip", 0, nullptr, nullptr);
+  if (r != HIPRTC_SUCCESS) {
+    job->error = std::string("hiprtcCreateProgram: ") + hiprtcGetErrorString(r);
+    return;
+  }
+  const char* opts[] = {"--offload-arch=gfx950", "-O3", "-ffp-contract=fast", "-Xclang", "-target-feature",
+                        "-Xclang", "-packed-fp32-ops"};
+  r = hiprtcCompileProgram(prog, (int)(sizeof opts / sizeof opts[0]), opts);
+  if (r != HIPRTC_SUCCESS) {
+    size_t n = 0;
+    hiprtcGetProgramLogSize(prog, &n);
+    std::string log(n, '\0');
+    if (n) hiprtcGetProgramLog(prog, &log[0]);
+    if (log.size() > 2000) log.resize(2000);
+    job->error = std::string("hiprtcCompileProgram: ") + hiprtcGetErrorString(r) + "\n" + log;
+    hiprtcDestroyProgram(&prog);
+    return;
+  }
+  size_t sz = 0;
+  hiprtcGetCodeSize(prog, &sz);
+  job->code.resize(sz);
+  hiprtcGetCode(prog, &job->code[0]);
+  hiprtcDestroyProgram(&prog);
+  if (dump && *dump) {
+    std::ofstream(std::string(dump) + "/" + job->kernels[0].first + ".co", std::ios::binary)
+        .write(job->code.data(), (std::streamsize)job->code.size());
+  }
+  job->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
 int compile_threads() {
@@ -810,6 +894,7 @@ Status ensure_compiled(const std::vector<std::string>& texts, std::vector<int>* 
       }
     }
     g_stats.kernels += (long long)missing.size();
+    for (auto& j : jobs) (j.by_clang ? g_stats.programs_clang : g_stats.programs_hiprtc) += 1;
     g_stats.compile_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   std::lock_guard<std::mutex> lk(g_mu);

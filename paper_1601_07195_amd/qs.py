@@ -65,7 +65,8 @@ _L.qs_precompile.argtypes = [_i, _i, _vp, _i, _dp, _i, _i, _vp]
 class QSJitStats(ctypes.Structure):
     _fields_ = [("kernels_compiled", ctypes.c_int64), ("kernels_cached", ctypes.c_int64),
                 ("modules_loaded", ctypes.c_int64), ("compile_seconds", ctypes.c_double),
-                ("kernels_from_disk", ctypes.c_int64)]
+                ("kernels_from_disk", ctypes.c_int64), ("programs_clang", ctypes.c_int64),
+                ("programs_hiprtc", ctypes.c_int64)]
 
 
 _L.qs_get_jit_stats.argtypes = [ctypes.POINTER(QSJitStats)]

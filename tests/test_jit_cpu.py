@@ -86,3 +86,33 @@ def test_disk_cache_serves_a_second_process(tmp_path):
     assert nk1 == nk2 > 0
     assert s1["kernels_compiled"] == nk1 and s1["kernels_from_disk"] == 0
     assert s2["kernels_compiled"] == 0 and s2["kernels_from_disk"] == nk2
+
+
+def test_hiprtc_fallback_compiles_too(tmp_path):
+    """QS_JIT_COMPILER=hiprtc takes the in-process path; the default takes
+    child clang processes when the ROCm driver exists."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys, json, numpy as np; sys.path.insert(0, %r)\n"
+            "import circuits as C, paper_1601_07195_amd.qs as Q\n"
+            "ops = C.random_circuit(12, 40, np.random.default_rng(23)).ops\n"
+            "print(json.dumps([Q.qs_precompile(12, Q.QS_C128, ops), Q.qs_get_jit_stats()]))\n" % root)
+    out = {}
+    for mode in ("hiprtc", "default"):
+        env = dict(os.environ)
+        env.pop("QS_JIT_CACHE_DIR", None)
+        if mode == "hiprtc":
+            env["QS_JIT_COMPILER"] = "hiprtc"
+        else:
+            env.pop("QS_JIT_COMPILER", None)
+        r = subprocess.run([sys.executable, "-c", code], env=env, check=True, capture_output=True, text=True)
+        out[mode] = json.loads(r.stdout.strip().splitlines()[-1])
+    nk, s = out["hiprtc"]
+    assert nk > 0 and s["programs_hiprtc"] > 0 and s["programs_clang"] == 0
+    nk2, s2 = out["default"]
+    assert nk2 == nk
+    if os.path.exists("/opt/rocm/llvm/bin/clang++"):
+        assert s2["programs_clang"] > 0 and s2["programs_hiprtc"] == 0
