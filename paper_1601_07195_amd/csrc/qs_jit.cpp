@@ -20,6 +20,7 @@
 // host threads, before the call's first launch.
 #include <fcntl.h>
 #include <hip/hiprtc.h>
+#include <signal.h>
 #include <spawn.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -737,9 +738,30 @@ bool compile_with_clang(const std::string& clang, const std::string& src, Compil
   pid_t pid = 0;
   const int rc = posix_spawn(&pid, clang.c_str(), &fa, nullptr, argv.data(), environ);
   posix_spawn_file_actions_destroy(&fa);
+  // wait for the child, at most kClangSeconds (a compile of one program
+  // takes seconds; a stuck one is killed and the job falls back to hipRTC)
+  constexpr int kClangSeconds = 300;
   int status = 0;
-  bool ok = rc == 0 && waitpid(pid, &status, 0) == pid && WIFEXITED(status) && WEXITSTATUS(status) == 0 &&
-            read_file(out, &job->code) && !job->code.empty();
+  bool exited = false;
+  if (rc == 0) {
+    const auto deadline = std::chrono::steady_clock::now() + std::chrono::seconds(kClangSeconds);
+    for (;;) {
+      const pid_t w = waitpid(pid, &status, WNOHANG);
+      if (w == pid) {
+        exited = true;
+        break;
+      }
+      if (w < 0) break;
+      if (std::chrono::steady_clock::now() > deadline) {
+        kill(pid, SIGKILL);
+        waitpid(pid, &status, 0);
+        break;
+      }
+      std::this_thread::sleep_for(std::chrono::milliseconds(5));
+    }
+  }
+  bool ok = exited && WIFEXITED(status) && WEXITSTATUS(status) == 0 && read_file(out, &job->code) &&
+            !job->code.empty();
   if (!ok) {
     std::string msg;
     read_file(log, &msg);
