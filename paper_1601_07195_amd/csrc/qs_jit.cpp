@@ -792,6 +792,9 @@ void compile_job(CompileJob* job) {
   if (!clang.empty()) {
     if (compile_with_clang(clang, src, job)) {
       job->by_clang = true;
+      if (dump && *dump)
+        std::ofstream(std::string(dump) + "/" + job->kernels[0].first + ".co", std::ios::binary)
+            .write(job->code.data(), (std::streamsize)job->code.size());
       job->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
       return;
     }
