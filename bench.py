@@ -360,6 +360,8 @@ def large_section(Q, C, np, torch):
         info, _, _ = Q.qs_plan(n, dtype, circ.ops)
         pergate = sum((S if op["kind"] == C.OP_CU else 2 * S) for op in circ.ops)
         tc = timed(lambda: st.run(circ.ops), stream, 1)
+        winfo, _, _ = Q.qs_plan(n, dtype, circ.ops, flags=Q.QS_RUN_WIDE_TILES)
+        tw = timed(lambda: st.run(circ.ops, wide=True), stream, 1)
         qft = C.qft_circuit(n)
         qinfo, _, _ = Q.qs_plan(n, dtype, qft.ops)
         tq = timed(lambda: st.run(qft.ops), stream, 1)
@@ -371,7 +373,9 @@ def large_section(Q, C, np, torch):
             "circuit": {"gates": len(circ), "passes": info["passes"], "s": round(tc, 4),
                         "hbm_GBps": round(info["hbm_bytes"] / tc / 1e9, 1),
                         "effective_GBps_paper_def": round(pergate / tc / 1e9, 1),
-                        "paper_qft_only_s": {"33": 245.0, "34": 297.4}[str(n)]},
+                        "paper_qft_only_s": {"33": 245.0, "34": 297.4}[str(n)],
+                        "wide_tiles": {"passes": winfo["passes"], "s": round(tw, 4),
+                                       "hbm_GBps": round(winfo["hbm_bytes"] / tw / 1e9, 1)}},
             "qft_iqft_fused_vs_unfused": top,
             "qft_only": {"gates": len(qft), "passes": qinfo["passes"], "s": round(tq, 4),
                          "effective_GBps_paper_def": round(
@@ -791,6 +795,11 @@ def main():
     tgt_gbps = {k: 2 * S / statistics.median(v) / 1e9 for k, v in per_target.items()}
     cu_gbps = sorted(S / d / 1e9 for d in cu_t)
 
+    # the same circuit with wide tiles (fewer low qubits fixed per tile:
+    # fewer passes, each at a lower fraction of peak)
+    wide_info, _, _ = Q.qs_plan(n, dtype, circ.ops, flags=Q.QS_RUN_WIDE_TILES)
+    t_wide = timed(lambda: st.run(circ.ops, wide=True), stream, 3)
+
     # STREAM copy (B_mem, Sec. 5.2) on a 2 x 4 GiB pair of buffers
     cs = 4 << 30
     src = torch.empty(cs // 8, dtype=torch.float64, device="cuda")
@@ -877,6 +886,9 @@ def main():
             "circuit_fused_passes": plan_info["fused"],
             "circuit_hbm_GBps": round(bytes_circ / statistics.median(circ_t) / 1e9, 1),
             "circuit_effective_GBps_paper_def": round(bytes_circ_pergate / statistics.median(circ_t) / 1e9, 1),
+            "circuit_wide_tiles": {"ms": round(t_wide * 1e3, 3), "passes": wide_info["passes"],
+                                   "hbm_GBps": round(wide_info["hbm_bytes"] / t_wide / 1e9, 1),
+                                   "pass_frac": round(wide_info["hbm_bytes"] / t_wide / 1e9 / PEAK_HBM_GBPS, 4)},
             "probabilities_GBps": round(S / statistics.median(probs_t) / 1e9, 1),
         },
         "stream_copy": {"GBps": round(copy_gbps, 1), "bytes": 2 * cs,

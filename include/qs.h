@@ -241,6 +241,12 @@ int qs_apply_kq(qs_state* s, int k, const int32_t* targets, const double* u);
  * Errors: QS_EINVAL for any malformed op (checked before any launch).
  */
 #define QS_RUN_NO_FUSION 1  /* one streaming pass per gate (no cache blocking) */
+/* Fused passes keep 4 (complex128) or 5 (complex64) low qubits in every
+ * tile instead of 6 / 7: three more free tile qubits, so fewer passes over
+ * the state, each moving its data in 256-byte contiguous runs instead of
+ * 1 KiB ones (a lower fraction of peak bandwidth per pass, less time per
+ * circuit).  Also accepted by qs_plan, qs_run_reordered and qs_precompile. */
+#define QS_RUN_WIDE_TILES 2
 int qs_run(qs_state* s, const qs_op* ops, int nops, const double* theta,
            int nparams, int flags);
 

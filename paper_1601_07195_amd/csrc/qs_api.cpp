@@ -328,12 +328,13 @@ int qs_precompile(int n, int dtype, const qs_op* ops, int nops, const double* th
   if (n < 1 || n > max_qubits(dtype)) return fail(QS_ERANGE, "qs_precompile: n out of range");
   if (nops < 0 || (nops > 0 && !ops)) return fail(QS_EINVAL, "qs_precompile: bad op list");
   if (nparams < 0) return fail(QS_EINVAL, "qs_precompile: nparams < 0");
-  if (flags & ~QS_PRECOMPILE_ADJOINT) return fail(QS_EINVAL, "qs_precompile: unknown flags");
+  if (flags & ~(QS_PRECOMPILE_ADJOINT | QS_RUN_WIDE_TILES)) return fail(QS_EINVAL, "qs_precompile: unknown flags");
   std::vector<qs::XGate> gates;
   Status st = qs::normalize_ops(n, ops, nops, theta, nparams, &gates);
   if (!st.good()) return done(st);
   int nk = 0;
-  st = qs::precompile_passes(n, dtype, gates, (flags & QS_PRECOMPILE_ADJOINT) != 0, &nk);
+  st = qs::precompile_passes(n, dtype, gates, (flags & QS_PRECOMPILE_ADJOINT) != 0,
+                             (flags & QS_RUN_WIDE_TILES) != 0, &nk);
   if (!st.good()) return done(st);
   if (nkernels) *nkernels = nk;
   return QS_OK;
@@ -405,7 +406,7 @@ int qs_run(qs_state* s, const qs_op* ops, int nops, const double* theta, int npa
   if (!valid_state(s)) return fail(QS_EINVAL, "qs_run: bad state");
   if (nops < 0 || (nops > 0 && !ops)) return fail(QS_EINVAL, "qs_run: bad op list");
   if (nparams < 0) return fail(QS_EINVAL, "qs_run: nparams < 0");
-  if (flags & ~QS_RUN_NO_FUSION) return fail(QS_EINVAL, "qs_run: unknown flags");
+  if (flags & ~(QS_RUN_NO_FUSION | QS_RUN_WIDE_TILES)) return fail(QS_EINVAL, "qs_run: unknown flags");
   std::vector<qs::XGate> gates;
   Status st = qs::normalize_ops(s->impl.n, ops, nops, theta, nparams, &gates);
   if (!st.good()) return done(st);
@@ -515,12 +516,13 @@ int qs_plan(int n, int dtype, const qs_op* ops, int nops, const double* theta, i
   if (n < 1 || n > max_qubits(dtype)) return fail(QS_ERANGE, "qs_plan: n out of range");
   if (nops < 0 || (nops > 0 && !ops)) return fail(QS_EINVAL, "qs_plan: bad op list");
   if (nparams < 0) return fail(QS_EINVAL, "qs_plan: nparams < 0");
-  if (flags & ~QS_RUN_NO_FUSION) return fail(QS_EINVAL, "qs_plan: unknown flags");
+  if (flags & ~(QS_RUN_NO_FUSION | QS_RUN_WIDE_TILES)) return fail(QS_EINVAL, "qs_plan: unknown flags");
   std::vector<qs::XGate> gates;
   Status st = qs::normalize_ops(n, ops, nops, theta, nparams, &gates);
   if (!st.good()) return done(st);
   qs::Plan plan;
-  qs::plan_gates(n, dtype, gates, !(flags & QS_RUN_NO_FUSION), &plan);
+  qs::plan_gates(n, dtype, gates, !(flags & QS_RUN_NO_FUSION), &plan, true, 1 << 30, false,
+                 (flags & QS_RUN_WIDE_TILES) != 0);
   if (info) {
     memset(info, 0, sizeof(*info));
     const double S = (double)((size_t)1 << n) * (double)qs::amp_bytes(dtype);
@@ -583,7 +585,7 @@ int qs_run_reordered(qs_state* s, int nlocal, const qs_op* ops, int nops, const 
   if (nlocal < 1 || nlocal > s->impl.n) return fail(QS_EINVAL, "qs_run_reordered: nlocal out of range");
   if (nops < 0 || (nops > 0 && !ops)) return fail(QS_EINVAL, "qs_run_reordered: bad op list");
   if (nparams < 0) return fail(QS_EINVAL, "qs_run_reordered: nparams < 0");
-  if (flags & ~QS_RUN_NO_FUSION) return fail(QS_EINVAL, "qs_run_reordered: unknown flags");
+  if (flags & ~(QS_RUN_NO_FUSION | QS_RUN_WIDE_TILES)) return fail(QS_EINVAL, "qs_run_reordered: unknown flags");
   std::vector<qs::XGate> gates;
   Status st = qs::normalize_ops(s->impl.n, ops, nops, theta, nparams, &gates);
   if (!st.good()) return done(st);

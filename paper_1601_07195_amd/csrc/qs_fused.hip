@@ -725,10 +725,10 @@ static Status launch_compiled(StateImpl* s, const JitPass& jp, unsigned grid, vo
 }
 
 Status precompile_passes(int n, int dtype, const std::vector<XGate>& gates, bool adjoint,
-                         int* nkernels) {
+                         bool wide, int* nkernels) {
   std::vector<JitPass> jp;
   Plan plan;
-  plan_gates(n, dtype, gates, true, &plan);
+  plan_gates(n, dtype, gates, true, &plan, true, 1 << 30, false, wide);
   Status st = jit_prepare(plan, n, dtype, false, &jp);
   if (!st.good()) return st;
   std::vector<int> used;
@@ -753,8 +753,9 @@ Status precompile_passes(int n, int dtype, const std::vector<XGate>& gates, bool
 
 Status run_gates(StateImpl* s, const std::vector<XGate>& gates, int flags) {
   Plan plan;
-  plan_gates(s->n, s->dtype, gates, !(flags & QS_RUN_NO_FUSION), &plan);
-  const FuseGeom G = fuse_geom(s->dtype);
+  plan_gates(s->n, s->dtype, gates, !(flags & QS_RUN_NO_FUSION), &plan, true, 1 << 30, false,
+             (flags & QS_RUN_WIDE_TILES) != 0);
+  const FuseGeom G = plan.geom;
   std::vector<JitPass> jp;
   if (use_compiled_passes(s)) {
     Status st = jit_prepare(plan, s->n, s->dtype, false, &jp);
@@ -830,7 +831,7 @@ Status run_adjoint_fused(StateImpl* s, StateImpl* lam, const std::vector<XGate>&
                          std::vector<int>* rows, double** slot_sums_dev) {
   Plan plan;
   plan_gates(s->n, s->dtype, rev, true, &plan, /*allow_single=*/false, kAdjMaxSlots, /*grad=*/true);
-  const FuseGeom G = fuse_geom(s->dtype);
+  const FuseGeom G = plan.geom;
   std::vector<JitPass> jp;
   Status st;
   if (use_compiled_passes(s)) {

@@ -144,7 +144,10 @@ struct FuseGeom {
   int lane0;  // first lane tile bit (0 for complex128; 1 for complex64, whose
               // tile bit 0 is inside the 16-byte unit)
 };
-FuseGeom fuse_geom(int dtype);
+// wide: fewer low qubits fixed in every tile (4 at complex128, 5 at
+// complex64, instead of 6 / 7): three more free tile qubits per pass, so
+// fewer passes, each moving its data in 256-byte contiguous runs.
+FuseGeom fuse_geom(int dtype, bool wide = false);
 
 struct FMap {
   int8_t thr[8];  // tile bit held by thread-index bit i
@@ -191,6 +194,7 @@ struct Pass {
   int remaps;
 };
 struct Plan {
+  FuseGeom geom;  // the tile geometry the plan was made for
   std::vector<Pass> passes;
   std::vector<FOp> ops;
   std::vector<FMap> maps;
@@ -210,7 +214,8 @@ struct Plan {
 // never merged with other gates; otherwise consecutive gates on the same
 // target and control may be merged into one op.
 void plan_gates(int n, int dtype, const std::vector<XGate>& gates, bool fuse, Plan* out,
-                bool allow_single = true, int max_grad = 1 << 30, bool grad = false);
+                bool allow_single = true, int max_grad = 1 << 30, bool grad = false,
+                bool wide = false);
 
 // Fused adjoint reverse sweep (n >= tile bits): `rev` holds the daggered
 // gates in reverse order; rotations keep their kind and carry in `param` the
@@ -256,7 +261,7 @@ constexpr int kJitAutoMinQubits = 26;
 // Plan a gate list as qs_run would (adjoint: also the reverse sweep of
 // qs_grad_adjoint) and compile its pass kernels; *nkernels: how many.
 Status precompile_passes(int n, int dtype, const std::vector<XGate>& gates, bool adjoint,
-                         int* nkernels);
+                         bool wide, int* nkernels);
 // The reverse sweep's gate list: U_j^dagger in reverse order.
 void reverse_daggered(const std::vector<XGate>& gates, std::vector<XGate>* rev);
 

@@ -139,7 +139,7 @@ class PassEmitter {
  public:
   PassEmitter(const Plan& plan, const Pass& p, int n, int dtype, bool adj)
       : plan_(plan), p_(p), n_(n), adj_(adj) {
-    const FuseGeom G = fuse_geom(dtype);
+    const FuseGeom G = plan.geom;
     g_.dtype = dtype;
     g_.nreg = G.nreg;
     g_.RA = 1 << G.nreg;
@@ -249,20 +249,38 @@ class PassEmitter {
     return name;
   }
 
+  // Offset, in 16-byte units, of this lane's bits under mapping m: the lane
+  // index itself when the lanes hold the lowest unit bits (contiguous
+  // 1 KiB per access), else each lane bit placed at its qubit.
+  std::string lane_part(const FMap& m) const {
+    const int sh = g_.c64 ? 1 : 0;  // unit bit = qubit - 1 at complex64
+    bool plain = true;
+    for (int i = 0; i < 6; ++i) plain &= gq(m.thr[i]) - sh == i;
+    if (plain) return "(unsigned long long)lane";
+    std::string e = "(0ull";
+    for (int i = 0; i < 6; ++i) {
+      char b[96];
+      snprintf(b, sizeof b, " | ((unsigned long long)((lane >> %d) & 1) << %d)", i, gq(m.thr[i]) - sh);
+      e += b;
+    }
+    return e + ")";
+  }
+
   void emit_load(const char* XR, const char* XI, const char* ptr) {
     const FMap& m = plan_.maps[p_.map_load];
     src_("    {");
     src_("      const unsigned long long ub = base | %s;", wave_part(m).c_str());
+    src_("      const unsigned long long lo_ = %s;", lane_part(m).c_str());
     if (!g_.c64) {
       src_("      const qs_d2* pa = %s + ub;", ptr);
       for (int r = 0; r < g_.RA; ++r) {
-        src_("      { const qs_d2 v = __builtin_nontemporal_load(pa + %lluull + lane); %s[%d] = v.x; %s[%d] = v.y; }",
+        src_("      { const qs_d2 v = __builtin_nontemporal_load(pa + %lluull + lo_); %s[%d] = v.x; %s[%d] = v.y; }",
              reg_part(m, r), XR, r, XI, r);
       }
     } else {
       src_("      const qs_f4* pa = %s + (ub >> 1);", ptr);
       for (int r = 0; r < g_.RA; r += 2) {
-        src_("      { const qs_f4 v = __builtin_nontemporal_load(pa + %lluull + lane); %s[%d] = v.x; %s[%d] = v.y; "
+        src_("      { const qs_f4 v = __builtin_nontemporal_load(pa + %lluull + lo_); %s[%d] = v.x; %s[%d] = v.y; "
              "%s[%d] = v.z; %s[%d] = v.w; }",
              reg_part(m, r) >> 1, XR, r, XI, r, XR, r + 1, XI, r + 1);
       }
@@ -274,15 +292,16 @@ class PassEmitter {
     const FMap& m = plan_.maps[p_.map_store];
     src_("    {");
     src_("      const unsigned long long ub = base | %s;", wave_part(m).c_str());
+    src_("      const unsigned long long lo_ = %s;", lane_part(m).c_str());
     if (!g_.c64) {
       src_("      qs_d2* pa = %s + ub;", ptr);
       for (int r = 0; r < g_.RA; ++r)
-        src_("      __builtin_nontemporal_store(qs_d2{%s[%d], %s[%d]}, pa + %lluull + lane);", XR, r, XI, r,
+        src_("      __builtin_nontemporal_store(qs_d2{%s[%d], %s[%d]}, pa + %lluull + lo_);", XR, r, XI, r,
              reg_part(m, r));
     } else {
       src_("      qs_f4* pa = %s + (ub >> 1);", ptr);
       for (int r = 0; r < g_.RA; r += 2)
-        src_("      __builtin_nontemporal_store(qs_f4{%s[%d], %s[%d], %s[%d], %s[%d]}, pa + %lluull + lane);", XR,
+        src_("      __builtin_nontemporal_store(qs_f4{%s[%d], %s[%d], %s[%d], %s[%d]}, pa + %lluull + lo_);", XR,
              r, XI, r, XR, r + 1, XI, r + 1, reg_part(m, r) >> 1);
     }
     src_("    }");

@@ -28,17 +28,17 @@
 
 namespace qs {
 
-FuseGeom fuse_geom(int dtype) {
+FuseGeom fuse_geom(int dtype, bool wide) {
   FuseGeom g;
   // 8 (complex128) or 16 (complex64) amplitudes per thread: more register
   // bits raise register pressure past two waves per SIMD on gfx950.
   if (dtype == QS_C128) {
     g.nreg = 3;
-    g.L = 6;
+    g.L = wide ? 4 : 6;
     g.lane0 = 0;
   } else {
     g.nreg = 4;
-    g.L = 7;
+    g.L = wide ? 5 : 7;
     g.lane0 = 1;
   }
   g.T = g.nreg + kFuseThreadBits;
@@ -133,7 +133,7 @@ FMap to_fmap(const Mapping& m) {
 }  // namespace
 
 void plan_gates(int n, int dtype, const std::vector<XGate>& gates, bool fuse, Plan* out,
-                bool allow_single, int max_grad, bool grad) {
+                bool allow_single, int max_grad, bool grad, bool wide) {
   out->passes.clear();
   out->ops.clear();
   out->maps.clear();
@@ -142,7 +142,8 @@ void plan_gates(int n, int dtype, const std::vector<XGate>& gates, bool fuse, Pl
   out->run_tab.clear();
   const int N = (int)gates.size();
   out->pass_of.assign(N, -1);
-  const FuseGeom G = fuse_geom(dtype);
+  const FuseGeom G = fuse_geom(dtype, wide);
+  out->geom = G;
 
   auto stream_pass = [&](int g) {
     Pass p;

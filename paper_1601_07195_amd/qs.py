@@ -25,6 +25,7 @@ QS_C64, QS_C128 = 1, 2
 QS_MAX_QUBITS_C128, QS_MAX_QUBITS_C64 = 33, 34
 QS_OP_U, QS_OP_CU, QS_OP_RX, QS_OP_RY, QS_OP_RZ = 0, 1, 2, 3, 4
 QS_RUN_NO_FUSION = 1
+QS_RUN_WIDE_TILES = 2
 QS_ADJ_STATE_IS_FINAL = 1
 QS_BATCH_MAX_QUBITS = 24
 QS_KQ_MAX = 5
@@ -486,8 +487,8 @@ class State:
         qs_apply_kq(self.handle, targets, u)
         return self
 
-    def run(self, ops, theta=None, fuse: bool = True) -> "State":
-        qs_run(self.handle, ops, theta, 0 if fuse else QS_RUN_NO_FUSION)
+    def run(self, ops, theta=None, fuse: bool = True, wide: bool = False) -> "State":
+        qs_run(self.handle, ops, theta, (0 if fuse else QS_RUN_NO_FUSION) | (QS_RUN_WIDE_TILES if wide else 0))
         return self
 
     def permute_qubits(self, perm) -> "State":

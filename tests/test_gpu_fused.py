@@ -178,3 +178,21 @@ def test_qft_iqft_fused_and_unfused(Q, name, n, fused):
         assert info["passes"] < ngates
     else:
         assert info["passes"] == ngates and info["fused"] == 0
+
+
+@pytest.mark.parametrize("name,n", [("c128", 12), ("c128", 17), ("c64", 13), ("c64", 18)])
+def test_wide_tiles(Q, name, n):
+    """QS_RUN_WIDE_TILES: tiles fix fewer low qubits (lanes also hold free
+    tile qubits), so loads and stores use shorter contiguous runs and the
+    plan has fewer passes; random gates, phase blocks and a QFT against the
+    oracle."""
+    rng = np.random.default_rng(950 + n)
+    ops = np.concatenate([C.random_circuit(n, 250, rng).ops, phase_blocks(n, 20, rng), C.qft_circuit(n).ops])
+    psi = random_state(n, rng)
+    st = to_gpu_state(Q, psi, dt(Q, name))
+    st.run(ops, wide=True)
+    ref = O.run(ops, n, psi=rounded_input(psi, name == "c64"))
+    assert np.abs(st.numpy() - ref).max() <= bound(name, len(ops))
+    narrow, _, _ = Q.qs_plan(n, dt(Q, name), ops)
+    wide, _, _ = Q.qs_plan(n, dt(Q, name), ops, flags=Q.QS_RUN_WIDE_TILES)
+    assert wide["passes"] <= narrow["passes"]

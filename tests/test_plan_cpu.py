@@ -134,3 +134,18 @@ def test_table2_printed_bounds_follow_from_the_byte_model(Q):
             ops = C.op_cu(n - 2, n - 1, u)
         info, *_ = Q.qs_plan_reorder(n, m, ops)
         assert info["traffic_pairwise"] * shard == 2 ** (m + x), (case, info)
+
+
+def test_wide_tiles_plan_fewer_passes():
+    """Fixing fewer low qubits in each tile frees three tile qubits per pass:
+    the 1000-gate random circuit at n = 30 needs fewer passes (and moves
+    fewer bytes) at both amplitude types."""
+    import numpy as np
+    import circuits as C
+    import paper_1601_07195_amd.qs as Q
+    ops = C.random_circuit(30, 1000, np.random.default_rng(C.SEED_BASE + 1)).ops
+    for dt in (Q.QS_C128, Q.QS_C64):
+        narrow, _, _ = Q.qs_plan(30, dt, ops)
+        wide, order, pass_of = Q.qs_plan(30, dt, ops, flags=Q.QS_RUN_WIDE_TILES)
+        assert wide["passes"] < narrow["passes"] and wide["hbm_bytes"] < narrow["hbm_bytes"]
+        assert sorted(order.tolist()) == list(range(len(ops)))
