@@ -52,6 +52,7 @@ extern "C" {
 #define QS_EHIP (-3)        /* a HIP runtime call or kernel launch failed */
 #define QS_ENODEV (-4)      /* no usable gfx950 device */
 #define QS_ERANGE (-5)      /* size out of range (n too large, buffer too small) */
+#define QS_EVERIFY (-6)     /* a QS_RUN_VERIFY check failed */
 
 /* Amplitude types. */
 #define QS_C64 1            /* complex64: float re, float im */
@@ -247,8 +248,21 @@ int qs_apply_kq(qs_state* s, int k, const int32_t* targets, const double* u);
  * 1 KiB ones (a lower fraction of peak bandwidth per pass, less time per
  * circuit).  Also accepted by qs_plan, qs_run_reordered and qs_precompile. */
 #define QS_RUN_WIDE_TILES 2
+/* Debug check (costs a scratch copy of the state and a second, unfused
+ * run): the list runs as asked, and also, on a copy of the input, as one
+ * streaming kernel per gate (Eq. 2 / 3 gate by gate); the call fails with
+ * QS_EVERIFY when the two results differ, or the norm moves, by more than
+ * rounding allows (64 units in the last place of the amplitude type times
+ * sqrt(gates + 1)).  A non-unitary gate (the paper assumes unitary ones,
+ * Sec. 2) fails the norm check.  qs_get_verify returns the last figures. */
+#define QS_RUN_VERIFY 4
 int qs_run(qs_state* s, const qs_op* ops, int nops, const double* theta,
            int nparams, int flags);
+
+/* Results of the state's last QS_RUN_VERIFY run: max_i |fused_i - per-gate_i|
+ * and |<psi|psi>_after - <psi|psi>_before| (-1 before any verified run).
+ * Either pointer may be NULL.  Errors: QS_EINVAL (bad state). */
+int qs_get_verify(qs_state* s, double* max_abs_diff, double* norm_drift);
 
 /*
  * Qubit reordering in place (the state reordering of Sec. 6): qubit q is

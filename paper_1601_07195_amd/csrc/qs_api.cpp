@@ -5,6 +5,9 @@
 // first HIP call, so a rejected call queues nothing.
 #include <hip/hip_runtime.h>
 #include <math.h>
+
+#include <algorithm>
+#include <cmath>
 #include <string.h>
 
 #include <new>
@@ -195,6 +198,7 @@ const char* qs_strerror(int code) {
     case QS_EHIP: return "HIP runtime error";
     case QS_ENODEV: return "no usable GPU device";
     case QS_ERANGE: return "size out of range";
+    case QS_EVERIFY: return "verification failed";
     default: return "unknown status";
   }
 }
@@ -402,15 +406,77 @@ int qs_permute_qubits(qs_state* s, const int32_t* perm) {
   return done(qs::launch_permute(&s->impl, perm));
 }
 
+// QS_RUN_VERIFY: the list runs as asked on the state and, on a scratch copy
+// of the input, as one streaming kernel per gate; the two results and the
+// norm before and after are compared.
+static Status run_verified(qs::StateImpl* s, const std::vector<qs::XGate>& gates, int flags) {
+  using qs::Status;
+  double norm0 = 0.0, norm1 = 0.0;
+  Status st = qs::launch_probabilities(s, nullptr, &norm0, nullptr);
+  if (!st.good()) return st;
+  const size_t bytes = ((size_t)1 << s->n) * qs::amp_bytes(s->dtype);
+  void* copy = nullptr;
+  st = qs::hip_status(hipMalloc(&copy, bytes), "verify: scratch state");
+  if (!st.good()) return st;
+  qs::StateImpl twin;
+  twin.n = s->n;
+  twin.dtype = s->dtype;
+  twin.ptr = copy;
+  twin.bytes = bytes;
+  twin.stream = s->stream;
+  twin.device = s->device;
+  twin.exec = QS_EXEC_INTERPRETED;
+  st = qs::hip_status(hipMemcpyAsync(copy, s->ptr, bytes, hipMemcpyDeviceToDevice, s->stream), "verify: copy");
+  if (st.good()) st = qs::run_gates(s, gates, flags);
+  if (st.good()) st = qs::run_gates(&twin, gates, QS_RUN_NO_FUSION);
+  double diff = 0.0;
+  if (st.good()) st = qs::max_abs_diff(s, copy, &diff);
+  if (st.good()) st = qs::launch_probabilities(s, nullptr, &norm1, nullptr);
+  (void)hipStreamSynchronize(s->stream);
+  (void)hipFree(copy);
+  if (twin.red.ptr) (void)hipFree(twin.red.ptr);
+  if (twin.scal.ptr) (void)hipFree(twin.scal.ptr);
+  if (twin.table.ptr) (void)hipFree(twin.table.ptr);
+  if (twin.stage.host) (void)hipHostFree(twin.stage.host);
+  if (twin.stage.done) (void)hipEventDestroy(twin.stage.done);
+  if (twin.result_host) (void)hipHostFree(twin.result_host);
+  if (!st.good()) return st;
+  const double drift = std::fabs(norm1 - norm0);
+  s->verify_diff = diff;
+  s->verify_drift = drift;
+  // rounding of a unitary gate list: about one unit in the last place of
+  // the amplitude type per gate on the way, grown like sqrt(gates)
+  const double eps = s->dtype == QS_C128 ? 1.1e-16 : 6e-8;
+  const double tol = 64.0 * eps * std::sqrt((double)gates.size() + 1.0) * std::max(1.0, std::sqrt(norm0));
+  if (diff > tol || drift > tol * std::max(1.0, norm0)) {
+    Status bad;
+    bad.code = QS_EVERIFY;
+    bad.msg = "qs_run verify: fused and per-gate results differ by " + std::to_string(diff) +
+              ", norm^2 drifted by " + std::to_string(drift) + " (tolerance " + std::to_string(tol) +
+              "); a non-unitary gate also fails this check";
+    return bad;
+  }
+  return Status::ok();
+}
+
 int qs_run(qs_state* s, const qs_op* ops, int nops, const double* theta, int nparams, int flags) {
   if (!valid_state(s)) return fail(QS_EINVAL, "qs_run: bad state");
   if (nops < 0 || (nops > 0 && !ops)) return fail(QS_EINVAL, "qs_run: bad op list");
   if (nparams < 0) return fail(QS_EINVAL, "qs_run: nparams < 0");
-  if (flags & ~(QS_RUN_NO_FUSION | QS_RUN_WIDE_TILES)) return fail(QS_EINVAL, "qs_run: unknown flags");
+  if (flags & ~(QS_RUN_NO_FUSION | QS_RUN_WIDE_TILES | QS_RUN_VERIFY))
+    return fail(QS_EINVAL, "qs_run: unknown flags");
   std::vector<qs::XGate> gates;
   Status st = qs::normalize_ops(s->impl.n, ops, nops, theta, nparams, &gates);
   if (!st.good()) return done(st);
-  return done(qs::run_gates(&s->impl, gates, flags));
+  if (!(flags & QS_RUN_VERIFY)) return done(qs::run_gates(&s->impl, gates, flags));
+  return done(run_verified(&s->impl, gates, flags & ~QS_RUN_VERIFY));
+}
+
+int qs_get_verify(qs_state* s, double* max_abs_diff, double* norm_drift) {
+  if (!valid_state(s)) return fail(QS_EINVAL, "qs_get_verify: bad state");
+  if (max_abs_diff) *max_abs_diff = s->impl.verify_diff;
+  if (norm_drift) *norm_drift = s->impl.verify_drift;
+  return QS_OK;
 }
 
 static int check_terms(const char* who, int nterms, const uint64_t* x, const uint64_t* z,

@@ -47,6 +47,7 @@ struct StateImpl {
   int cus = 0;       // compute units of the device (0 = not queried yet)
   int grid_limit = 0;  // cap on a fused pass's workgroups (0 = automatic)
   int exec = QS_EXEC_AUTO;  // fused passes: compiled per shape or interpreted
+  double verify_diff = -1.0, verify_drift = -1.0;  // last QS_RUN_VERIFY results
   DevBuf red;        // reduction partials
   DevBuf scal;       // small device results (energy)
   DevBuf table;      // uploaded tables
@@ -102,6 +103,8 @@ Status build_pauli_table(int n, int nterms, const uint64_t* x, const uint64_t* z
 Status launch_expect(StateImpl* s, const PauliTable& t, double* out_host);
 // dst = H src (asynchronous).
 Status launch_apply_pauli_sum(StateImpl* src, StateImpl* dst, const PauliTable& t);
+// max_i |a_i - b_i| for b a device state of a's shape (synchronises).
+Status max_abs_diff(StateImpl* a, const void* b, double* out_host);
 // <a|b> into device double2 at dev_out (asynchronous).
 Status launch_inner_dev(StateImpl* a, StateImpl* b, double* dev_out);
 

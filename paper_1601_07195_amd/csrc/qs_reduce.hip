@@ -560,4 +560,53 @@ Status launch_inner_dev(StateImpl* a, StateImpl* b, double* dev_out) {
   return last_launch("inner final");
 }
 
+// ------------------------------------------------------------ debug check
+// max_i |a_i - b_i| over two states of the same shape (|.| of the complex
+// difference, in double precision), one partial per workgroup.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_max_abs_diff(const T* __restrict__ a, const T* __restrict__ b, uint64_t count,
+               double* __restrict__ part) {
+  __shared__ double lds[kBlock];
+  double m = 0.0;
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += stride) {
+    const double dr = (double)a[i].x - (double)b[i].x, di = (double)a[i].y - (double)b[i].y;
+    m = fmax(m, sqrt(dr * dr + di * di));
+  }
+  lds[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) lds[threadIdx.x] = fmax(lds[threadIdx.x], lds[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = lds[0];
+}
+
+Status max_abs_diff(StateImpl* a, const void* b, double* out_host) {
+  const uint64_t count = 1ull << a->n;
+  const unsigned grid = (unsigned)std::min<uint64_t>(4096, (count + kBlock - 1) / kBlock);
+  Status st = ensure_dev(a, a->red, grid * sizeof(double));
+  if (!st.good()) return st;
+  double* part = (double*)a->red.ptr;
+  if (a->dtype == QS_C128)
+    hipLaunchKernelGGL(k_max_abs_diff<d2>, dim3(grid), dim3(kBlock), 0, a->stream, (const d2*)a->ptr,
+                       (const d2*)b, count, part);
+  else
+    hipLaunchKernelGGL(k_max_abs_diff<f2>, dim3(grid), dim3(kBlock), 0, a->stream, (const f2*)a->ptr,
+                       (const f2*)b, count, part);
+  st = hip_status(hipGetLastError(), "max_abs_diff");
+  if (!st.good()) return st;
+  std::vector<double> h(grid);
+  st = hip_status(hipMemcpyAsync(h.data(), part, grid * sizeof(double), hipMemcpyDeviceToHost, a->stream),
+                  "max_abs_diff copy");
+  if (!st.good()) return st;
+  st = hip_status(hipStreamSynchronize(a->stream), "max_abs_diff sync");
+  if (!st.good()) return st;
+  double m = 0.0;
+  for (double v : h) m = std::max(m, v);
+  *out_host = m;
+  return Status::ok();
+}
+
 }  // namespace qs

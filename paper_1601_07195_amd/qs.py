@@ -20,12 +20,13 @@ import torch  # loaded first: libqs binds to the HIP runtime torch already loade
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libqs.so")
 
-QS_OK, QS_EINVAL, QS_ENOMEM, QS_EHIP, QS_ENODEV, QS_ERANGE = 0, -1, -2, -3, -4, -5
+QS_OK, QS_EINVAL, QS_ENOMEM, QS_EHIP, QS_ENODEV, QS_ERANGE, QS_EVERIFY = 0, -1, -2, -3, -4, -5, -6
 QS_C64, QS_C128 = 1, 2
 QS_MAX_QUBITS_C128, QS_MAX_QUBITS_C64 = 33, 34
 QS_OP_U, QS_OP_CU, QS_OP_RX, QS_OP_RY, QS_OP_RZ = 0, 1, 2, 3, 4
 QS_RUN_NO_FUSION = 1
 QS_RUN_WIDE_TILES = 2
+QS_RUN_VERIFY = 4
 QS_ADJ_STATE_IS_FINAL = 1
 QS_BATCH_MAX_QUBITS = 24
 QS_KQ_MAX = 5
@@ -43,7 +44,7 @@ EXPORTED = ("qs_version", "qs_strerror", "qs_last_error", "qs_create", "qs_destr
             "qs_stream_copy", "qs_plan", "qs_batch_create", "qs_batch_run",
             "qs_batch_destroy", "qs_apply_kq", "qs_permute_qubits", "qs_plan_reorder",
             "qs_run_reordered", "qs_set_grid_limit", "qs_probabilities_noalloc",
-            "qs_set_fused_exec", "qs_precompile", "qs_get_jit_stats")
+            "qs_set_fused_exec", "qs_precompile", "qs_get_jit_stats", "qs_get_verify")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1601_07195_amd.build`")
@@ -60,6 +61,7 @@ _L.qs_destroy.argtypes = [_vp]
 _L.qs_set_stream.argtypes = [_vp, _vp]
 _L.qs_set_grid_limit.argtypes = [_vp, _i]
 _L.qs_set_fused_exec.argtypes = [_vp, _i]
+_L.qs_get_verify.argtypes = [_vp, _dp, _dp]
 _L.qs_precompile.argtypes = [_i, _i, _vp, _i, _dp, _i, _i, _vp]
 
 
@@ -316,6 +318,13 @@ def qs_plan(n: int, dtype: int, ops, theta=None, flags: int = 0):
     return d, order, pass_of
 
 
+def qs_get_verify(h: int):
+    """(max |fused - per-gate|, norm^2 drift) of the state's last verified run."""
+    d = np.zeros(2, dtype=np.float64)
+    _check(_L.qs_get_verify(h, _ptr(d[:1]), _ptr(d[1:])), "qs_get_verify")
+    return float(d[0]), float(d[1])
+
+
 def qs_set_fused_exec(h: int, mode: int) -> None:
     _check(_L.qs_set_fused_exec(h, mode), "qs_set_fused_exec")
 
@@ -487,8 +496,9 @@ class State:
         qs_apply_kq(self.handle, targets, u)
         return self
 
-    def run(self, ops, theta=None, fuse: bool = True, wide: bool = False) -> "State":
-        qs_run(self.handle, ops, theta, (0 if fuse else QS_RUN_NO_FUSION) | (QS_RUN_WIDE_TILES if wide else 0))
+    def run(self, ops, theta=None, fuse: bool = True, wide: bool = False, verify: bool = False) -> "State":
+        qs_run(self.handle, ops, theta, (0 if fuse else QS_RUN_NO_FUSION) | (QS_RUN_WIDE_TILES if wide else 0)
+               | (QS_RUN_VERIFY if verify else 0))
         return self
 
     def permute_qubits(self, perm) -> "State":

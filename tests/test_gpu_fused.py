@@ -196,3 +196,27 @@ def test_wide_tiles(Q, name, n):
     narrow, _, _ = Q.qs_plan(n, dt(Q, name), ops)
     wide, _, _ = Q.qs_plan(n, dt(Q, name), ops, flags=Q.QS_RUN_WIDE_TILES)
     assert wide["passes"] <= narrow["passes"]
+
+
+@pytest.mark.parametrize("name,n,wide", [("c128", 14, False), ("c128", 16, True), ("c64", 15, False),
+                                         ("c64", 17, True)])
+def test_verify_mode(Q, name, n, wide):
+    """QS_RUN_VERIFY runs the list as asked and, on a scratch copy, gate by
+    gate: a unitary list passes with per-gate agreement and no norm drift;
+    a non-unitary gate fails the check with QS_EVERIFY."""
+    rng = np.random.default_rng(980 + n)
+    ops = np.concatenate([C.random_circuit(n, 200, rng).ops, C.qft_circuit(n).ops])
+    psi = random_state(n, rng)
+    st = to_gpu_state(Q, psi, dt(Q, name))
+    st.run(ops, wide=wide, verify=True)
+    diff, drift = Q.qs_get_verify(st.handle)
+    ref = O.run(ops, n, psi=rounded_input(psi, name == "c64"))
+    assert np.abs(st.numpy() - ref).max() <= bound(name, len(ops))
+    lim = 1e-13 if name == "c128" else 1e-5
+    assert 0.0 <= diff <= lim and 0.0 <= drift <= lim
+    bad = C.random_circuit(n, 40, rng).ops
+    bad[7]["mat"] = C.mat_to_row(1.5 * np.eye(2))
+    with pytest.raises(Q.QSError) as err:
+        st.run(bad, wide=wide, verify=True)
+    assert err.value.code == Q.QS_EVERIFY
+    assert Q.qs_get_verify(st.handle)[1] > 0.1
