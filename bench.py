@@ -577,6 +577,27 @@ def adjoint_section(Q, C, np, torch, ps_pairs):
         for _ in range(reps):
             e64, g64 = adj64()
         rec["c64_adjoint_s"] = round((time.perf_counter() - t0) / reps, 4)
+        if n == 28:
+            # both sweeps on wide tiles (fewer passes), complex128 and complex64
+            for nm, s_, l_ in (("c128", None, None), ("c64", s64, l64)):
+                if s_ is None:
+                    s_ = Q.State(n, Q.QS_C128, stream=stream)
+                    l_ = Q.State(n, Q.QS_C128, stream=stream, init=False)
+
+                def adjw():
+                    s_.init_basis(0)
+                    return Q.qs_grad_adjoint(s_.handle, circ.ops, circ.theta, x, z, ham.coeff, l_.handle,
+                                             Q.QS_ADJ_WIDE_TILES)
+
+                adjw()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ew, gw = adjw()
+                rec[f"{nm}_adjoint_wide_tiles_s"] = round(time.perf_counter() - t0, 4)
+                ref_e, ref_g = (e, g) if nm == "c128" else (e64, g64)
+                rec[f"{nm}_wide_tiles_max_abs_diff"] = {"energy": abs(ew - ref_e), "gradient": float(np.abs(gw - ref_g).max())}
+                del s_, l_
+                torch.cuda.empty_cache()
         rec["c64_max_abs_diff_vs_c128"] = {"energy": abs(e64 - e), "gradient": float(np.abs(g64 - g).max())}
         del s64, l64
         torch.cuda.empty_cache()

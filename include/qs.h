@@ -408,7 +408,7 @@ int qs_apply_pauli_sum(qs_state* src, qs_state* dst, int nterms,
  *   lambda  second state (same n, dtype), used as workspace; overwritten
  *   flags   QS_ADJ_* bits: with QS_ADJ_STATE_IS_FINAL the state already
  *           holds psi(theta) (e.g. left by qs_run) and the forward sweep is
- *           skipped
+ *           skipped; QS_ADJ_WIDE_TILES plans both sweeps on wide tiles
  *   energy  host, 1 double (may be NULL)
  *   grad    host, nparams doubles (dE/dtheta[p], summed over every rotation
  *           that uses parameter p)
@@ -416,6 +416,9 @@ int qs_apply_pauli_sum(qs_state* src, qs_state* dst, int nterms,
  * fixed order.  Synchronises.
  */
 #define QS_ADJ_STATE_IS_FINAL 1
+/* fused forward and reverse passes on wide tiles (as QS_RUN_WIDE_TILES):
+ * fewer passes, each at a lower fraction of peak bandwidth */
+#define QS_ADJ_WIDE_TILES 2
 int qs_grad_adjoint(qs_state* s, const qs_op* ops, int nops,
                     const double* theta, int nparams, int nterms,
                     const uint64_t* x, const uint64_t* z, const double* coeff,

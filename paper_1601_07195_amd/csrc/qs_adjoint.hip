@@ -151,8 +151,9 @@ void reverse_daggered(const std::vector<XGate>& gates, std::vector<XGate>* rev) 
 Status run_adjoint(StateImpl* s, StateImpl* lam, const std::vector<XGate>& gates, int nparams,
                    const PauliTable& h, int flags, double* energy, double* grad) {
   Status st;
+  const bool wide = (flags & QS_ADJ_WIDE_TILES) != 0;
   if (!(flags & QS_ADJ_STATE_IS_FINAL)) {
-    st = run_gates(s, gates, 0);
+    st = run_gates(s, gates, wide ? QS_RUN_WIDE_TILES : 0);
     if (!st.good()) return st;
   }
   // lambda = H psi_N, queued on the state's stream.
@@ -173,7 +174,7 @@ Status run_adjoint(StateImpl* s, StateImpl* lam, const std::vector<XGate>& gates
   if (s->n >= fuse_geom(s->dtype).T) {
     std::vector<XGate> rev;
     reverse_daggered(gates, &rev);
-    st = run_adjoint_fused(s, &lam_on_s, rev, &rows, &sums);
+    st = run_adjoint_fused(s, &lam_on_s, rev, &rows, &sums, wide);
     if (!st.good()) return st;
   } else {
     for (int g = (int)gates.size() - 1; g >= 0; --g)

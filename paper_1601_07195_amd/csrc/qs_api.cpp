@@ -564,7 +564,8 @@ int qs_grad_adjoint(qs_state* s, const qs_op* ops, int nops, const double* theta
   if (s->impl.ptr == lambda->impl.ptr) return fail(QS_EINVAL, "qs_grad_adjoint: lambda aliases the state");
   if (nops < 0 || (nops > 0 && !ops)) return fail(QS_EINVAL, "qs_grad_adjoint: bad op list");
   if (nparams < 0 || (nparams > 0 && !grad)) return fail(QS_EINVAL, "qs_grad_adjoint: bad gradient buffer");
-  if (flags & ~QS_ADJ_STATE_IS_FINAL) return fail(QS_EINVAL, "qs_grad_adjoint: unknown flags");
+  if (flags & ~(QS_ADJ_STATE_IS_FINAL | QS_ADJ_WIDE_TILES))
+    return fail(QS_EINVAL, "qs_grad_adjoint: unknown flags");
   int rc = check_terms("qs_grad_adjoint", nterms, x, z, coeff);
   if (rc) return rc;
   std::vector<qs::XGate> gates;

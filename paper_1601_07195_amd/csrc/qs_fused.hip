@@ -742,7 +742,7 @@ Status precompile_passes(int n, int dtype, const std::vector<XGate>& gates, bool
     std::vector<XGate> rev;
     reverse_daggered(gates, &rev);
     Plan ap;
-    plan_gates(n, dtype, rev, true, &ap, /*allow_single=*/false, kAdjMaxSlots, /*grad=*/true);
+    plan_gates(n, dtype, rev, true, &ap, /*allow_single=*/false, kAdjMaxSlots, /*grad=*/true, wide);
     st = jit_prepare(ap, n, dtype, true, &jp);
     if (!st.good()) return st;
     count(jp);
@@ -828,9 +828,9 @@ static int device_cus(StateImpl* s) {
 constexpr int kAdjWgPerCu = 3;  // resident adjoint workgroups per CU (three waves per SIMD)
 
 Status run_adjoint_fused(StateImpl* s, StateImpl* lam, const std::vector<XGate>& rev,
-                         std::vector<int>* rows, double** slot_sums_dev) {
+                         std::vector<int>* rows, double** slot_sums_dev, bool wide) {
   Plan plan;
-  plan_gates(s->n, s->dtype, rev, true, &plan, /*allow_single=*/false, kAdjMaxSlots, /*grad=*/true);
+  plan_gates(s->n, s->dtype, rev, true, &plan, /*allow_single=*/false, kAdjMaxSlots, /*grad=*/true, wide);
   const FuseGeom G = plan.geom;
   std::vector<JitPass> jp;
   Status st;

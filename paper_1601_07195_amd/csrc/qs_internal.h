@@ -226,7 +226,7 @@ void plan_gates(int n, int dtype, const std::vector<XGate>& gates, bool fuse, Pl
 // slot i and slot_sums_dev[i] (device, in the state's reduction buffer) its
 // contribution, summed in a fixed order.
 Status run_adjoint_fused(StateImpl* s, StateImpl* lam, const std::vector<XGate>& rev,
-                         std::vector<int>* rows, double** slot_sums_dev);
+                         std::vector<int>* rows, double** slot_sums_dev, bool wide = false);
 // out[r] = sum of part[r * ncols + c] over c, fixed order (one workgroup per row).
 Status launch_sum_rows(StateImpl* s, const double* part, int nrows, int ncols, double* out);
 constexpr int kAdjMaxSlots = 64;  // gradient rows per fused adjoint pass

@@ -28,6 +28,7 @@ QS_RUN_NO_FUSION = 1
 QS_RUN_WIDE_TILES = 2
 QS_RUN_VERIFY = 4
 QS_ADJ_STATE_IS_FINAL = 1
+QS_ADJ_WIDE_TILES = 2
 QS_BATCH_MAX_QUBITS = 24
 QS_KQ_MAX = 5
 QS_NOALLOC_SCRATCH_BYTES = 2048 * 35 * 8 + 35 * 8
@@ -522,10 +523,11 @@ class State:
         return self.tensor.detach().cpu().numpy().astype(np.complex128)
 
 
-def grad_adjoint(state: State, lam: State, ops, theta, codes, coeff, state_is_final: bool = False):
+def grad_adjoint(state: State, lam: State, ops, theta, codes, coeff, state_is_final: bool = False,
+                 wide: bool = False):
     """Energy and adjoint gradient; see qs_grad_adjoint."""
     x, z = pauli_masks(codes)
-    flags = QS_ADJ_STATE_IS_FINAL if state_is_final else 0
+    flags = (QS_ADJ_STATE_IS_FINAL if state_is_final else 0) | (QS_ADJ_WIDE_TILES if wide else 0)
     return qs_grad_adjoint(state.handle, ops, theta, x, z, coeff, lam.handle, flags)
 
 

@@ -161,3 +161,22 @@ def test_fused_adjoint_reproducible(Q):
     a = adjoint(Q, circ, ham, Q.QS_C128)
     b = adjoint(Q, circ, ham, Q.QS_C128)
     assert a[0] == b[0] and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("name,n", [("c128", 13), ("c128", 16), ("c64", 14)])
+def test_fused_adjoint_wide_tiles(Q, name, n):
+    """QS_ADJ_WIDE_TILES plans the forward and reverse sweeps on wide tiles:
+    the same energy and gradient (parameter shift on the oracle)."""
+    circ, ham = C.workload_ansatz(n, 3, 25, seed=2100 + n)
+    dtype = Q.QS_C128 if name == "c128" else Q.QS_C64
+    st = Q.State(n, dtype)
+    lam = Q.State(n, dtype, init=False)
+    e, g = Q.grad_adjoint(st, lam, circ.ops, circ.theta, ham.codes, ham.coeff, wide=True)
+    re = O.energy(circ.ops, n, circ.theta, ham.codes, ham.coeff)
+    sample = list(range(0, circ.nparams, 4))
+    rg = O.grad_param_shift(circ.ops, n, circ.theta, ham.codes, ham.coeff, params=sample)
+    scale = max(1.0, np.abs(ham.coeff).sum())
+    if name == "c128":
+        assert abs(e - re) <= 1e-12 and np.abs(g[sample] - rg[sample]).max() <= 1e-10
+    else:
+        assert abs(e - re) <= 1e-4 * scale and np.abs(g[sample] - rg[sample]).max() <= 1e-4 * scale
