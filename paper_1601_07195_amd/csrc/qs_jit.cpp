@@ -73,6 +73,9 @@ struct Src {
   }
 };
 
+// Stands for the kernel's name in its text (the name is a hash of the text).
+const char* const kNamePlaceholder = "QS_PASS_NAME";
+
 // Device helpers shared by every generated kernel of a program.
 const char* kPrelude = R"(
 typedef double qs_d2 __attribute__((ext_vector_type(2)));
@@ -150,8 +153,9 @@ class PassEmitter {
     g_.es = g_.c64 ? 8 : 16;
   }
 
-  // Kernel text after its name; empty when the pass has a shape this
-  // generator does not take (the interpreter runs it then).
+  // The kernel's definition, with kNamePlaceholder for its name; empty when
+  // the pass has a shape this generator does not take (the interpreter runs
+  // it then).
   std::string body() {
     if (!check()) return std::string();
     emit();
@@ -489,6 +493,154 @@ class PassEmitter {
     src_("    }");
   }
 
+  // End of the run of uncontrolled diagonal ops that starts at op i (at
+  // least i + 1).
+  int diag_run_end(int i) const {
+    int j = i;
+    while (j < p_.op_first + p_.nops && (plan_.ops[j].kind & 255) == kOpDiag && (plan_.ops[j].ctl >> 8) == kNoBit)
+      ++j;
+    return j;
+  }
+
+  // Uncontrolled diagonal ops [i0, i1) in one go.  Diagonal unitaries
+  // commute, so the run's product is one factor per amplitude:
+  //   F(r) = T * prod_k A_k[bit k of r],
+  // T the product of the factors of ops whose target is a thread bit or
+  // outside the tile (one value per thread), A_k[b] the product of d_b over
+  // the ops on register bit k.  F is built over the register bits as a
+  // product tree and each amplitude is scaled once.  In the adjoint the
+  // gradient terms Im(conj(lambda_r) psi_r) are unchanged by a diagonal
+  // unitary applied to both tiles, so they are formed once for the run and
+  // each op's gradient is a signed sum of them.
+  void emit_diag_run(int i0, int i1) {
+    src_("    {  // ops %d-%d: %d uncontrolled diagonal ops", i0 - p_.op_first, i1 - 1 - p_.op_first, i1 - i0);
+    bool grad = false, grad_thr = false;
+    for (int i = i0; i < i1; ++i) {
+      const FOp& op = plan_.ops[i];
+      if (adj_ && op.aux >= 0) {
+        grad = true;
+        if ((op.tgt >> 8) != kInReg) grad_thr = true;
+      }
+    }
+    // complex64 keeps the terms (each costs four conversions to double);
+    // complex128 forms them again per op (two instructions each), which
+    // keeps fewer registers live
+    const bool keep = g_.c64;
+    auto term = [&](int r) {
+      char b[96];
+      if (keep)
+        snprintf(b, sizeof b, "w%d_", r);
+      else
+        snprintf(b, sizeof b, "QS_IMC(yr[%d], yi[%d], xr[%d], xi[%d])", r, r, r, r);
+      return std::string(b);
+    };
+    if (grad) {
+      if (keep)
+        for (int r = 0; r < g_.RA; ++r)
+          src_("      const double w%d_ = QS_IMC(yr[%d], yi[%d], xr[%d], xi[%d]);", r, r, r, r, r);
+      if (grad_thr) {
+        src_("      double wt_ = 0.0;");
+        for (int r = 0; r < g_.RA; ++r) src_("      wt_ += %s;", term(r).c_str());
+      }
+      for (int i = i0; i < i1; ++i) {
+        const FOp& op = plan_.ops[i];
+        if (op.aux < 0) continue;
+        const int tw = op.tgt >> 8, tix = op.tgt & 255;
+        src_("      {  // op %d: gradient, target %d/%d", i - p_.op_first, tw, tix);
+        if (tw == kInReg) {
+          src_("      double g_ = 0.0;");
+          for (int r = 0; r < g_.RA; ++r) src_("      g_ %s= %s;", ((r >> tix) & 1) ? "-" : "+", term(r).c_str());
+        } else {
+          src_("      double g_ = %s ? -wt_ : wt_;",
+               tw == kInThread ? thread_bit(tix).c_str() : outside_bit(tix).c_str());
+        }
+        emit_grad_store(op.aux);
+        src_("      }");
+      }
+    }
+    // T and the per-register-bit products; "one" marks a factor known to be 1
+    bool t_one = true;
+    for (int i = i0; i < i1; ++i)
+      if ((plan_.ops[i].tgt >> 8) != kInReg) {
+        src_("      R tr_, ti_;");
+        break;
+      }
+    std::vector<int> a_have(g_.nreg, 0);   // any op on register bit k
+    std::vector<int> a0_one(g_.nreg, 1);   // A_k[0] still 1 (phase ops only)
+    for (int i = i0; i < i1; ++i) {
+      const FOp& op = plan_.ops[i];
+      const int tw = op.tgt >> 8, tix = op.tgt & 255;
+      const bool phase = op.m[0] == 1.0 && op.m[1] == 0.0;
+      const int j = i - p_.op_first;
+      src_("      const double* m%d_ = %s->m;", j, opref(i).c_str());
+      if (tw == kInReg) {
+        if (!a_have[tix]) {
+          src_("      R a%d1r = (R)m%d_[6], a%d1i = (R)m%d_[7];", tix, j, tix, j);
+        } else {
+          src_("      QS_CMUL(a%d1r, a%d1i, (R)m%d_[6], (R)m%d_[7])", tix, tix, j, j);
+        }
+        if (!phase) {
+          if (a0_one[tix])
+            src_("      R a%d0r = (R)m%d_[0], a%d0i = (R)m%d_[1];", tix, j, tix, j);
+          else
+            src_("      QS_CMUL(a%d0r, a%d0i, (R)m%d_[0], (R)m%d_[1])", tix, tix, j, j);
+          a0_one[tix] = 0;
+        }
+        a_have[tix] = 1;
+      } else {
+        const std::string b = tw == kInThread ? thread_bit(tix) : outside_bit(tix);
+        src_("      {");
+        src_("        const bool s_ = %s;", b.c_str());
+        src_("        const R fr_ = s_ ? (R)m%d_[6] : (R)m%d_[0], fi_ = s_ ? (R)m%d_[7] : (R)m%d_[1];", j, j, j, j);
+        if (t_one)
+          src_("        tr_ = fr_; ti_ = fi_;");
+        else
+          src_("        QS_CMUL(tr_, ti_, fr_, fi_)");
+        src_("      }");
+        t_one = false;
+      }
+    }
+    // F over the registers: level k doubles the list with A_k
+    std::vector<std::string> fr(1, t_one ? "" : "tr_"), fi(1, t_one ? "" : "ti_");
+    int nf = 0;
+    for (int k = 0; k < g_.nreg; ++k) {
+      const int m = (int)fr.size();
+      std::vector<std::string> nr(2 * m), ni(2 * m);
+      for (int r = 0; r < m; ++r)
+        for (int b = 0; b < 2; ++b) {
+          const int o = r + b * m;
+          const bool a_one = !a_have[k] || (b == 0 && a0_one[k]);
+          char ar[16], ai[16];
+          snprintf(ar, sizeof ar, "a%d%dr", k, b);
+          snprintf(ai, sizeof ai, "a%d%di", k, b);
+          if (a_one) {
+            nr[o] = fr[r];
+            ni[o] = fi[r];
+          } else if (fr[r].empty()) {
+            nr[o] = ar;
+            ni[o] = ai;
+          } else {
+            char v[16];
+            snprintf(v, sizeof v, "f%d", nf++);
+            src_("      const R %sr = %s * %s - %s * %s, %si = %s * %s + %s * %s;", v, fr[r].c_str(), ar,
+                 fi[r].c_str(), ai, v, fr[r].c_str(), ai, fi[r].c_str(), ar);
+            nr[o] = std::string(v) + "r";
+            ni[o] = std::string(v) + "i";
+          }
+        }
+      fr.swap(nr);
+      fi.swap(ni);
+    }
+    // the list is indexed with register bit k at position k: entry
+    // r + b * 2^k at level k
+    for (int r = 0; r < g_.RA; ++r) {
+      if (fr[r].empty()) continue;
+      src_("      QS_SC(xr, xi, %d, %s, %s)", r, fr[r].c_str(), fi[r].c_str());
+      if (adj_) src_("      QS_SC(yr, yi, %d, %s, %s)", r, fr[r].c_str(), fi[r].c_str());
+    }
+    src_("    }");
+  }
+
   // A phase run (forward passes only): per-lane product of the run's
   // phases, then the target-bit-1 amplitudes scaled once.
   int emit_run(int i) {
@@ -545,6 +697,13 @@ class PassEmitter {
 
   void emit() {
     const char* VT = g_.c64 ? "qs_f4" : "qs_d2";
+    // Adjoint passes hold two tiles and a 32 KiB remap buffer plus the
+    // gradient slots, so LDS admits four workgroups per CU; without a hint
+    // the compiler spends registers down to two or three waves per SIMD.
+    // Four (128 registers, a few spilled) measured faster at both dtypes.
+    src_.s += "extern \"C\" __global__ void __launch_bounds__(256) ";
+    if (adj_) src_.s += "__attribute__((amdgpu_waves_per_eu(4))) ";
+    src_.s += kNamePlaceholder;
     if (adj_)
       src_("(%s* __restrict__ qa, %s* __restrict__ ql, const QsOp* __restrict__ ops, const char* __restrict__ maps, "
            "double* __restrict__ part, unsigned long long ntiles) {",
@@ -597,8 +756,11 @@ class PassEmitter {
     for (int i = p_.op_first; i < p_.op_first + p_.nops; ++i) {
       const FOp& op = plan_.ops[i];
       const int kind = op.kind & 255;
-      const int next = kind == kOpPhaseRun ? i + op.aux + 1 : i + 1;
-      release_upto(i);
+      // a run of uncontrolled diagonal ops is emitted as one op
+      const int run_end = kind == kOpDiag ? diag_run_end(i) : i + 1;
+      const bool diag_run = run_end - i >= 2;
+      const int next = kind == kOpPhaseRun ? i + op.aux + 1 : diag_run ? run_end : i + 1;
+      release_upto(diag_run ? run_end - 1 : i);
       // the next op that reads a record
       for (int j = next; j < p_.op_first + p_.nops; ++j) {
         const int k = plan_.ops[j].kind & 255;
@@ -614,6 +776,9 @@ class PassEmitter {
         if (adj_) emit_remap_tile("yr", "yi", op.aux, op.tgt);
       } else if (kind == kOpU) {
         emit_u(i);
+      } else if (kind == kOpDiag && diag_run) {
+        emit_diag_run(i, run_end);
+        i = run_end - 1;
       } else if (kind == kOpDiag) {
         emit_diag(i);
       } else if (kind == kOpPhaseRun) {
@@ -799,9 +964,11 @@ void compile_job(CompileJob* job) {
   const auto t0 = std::chrono::steady_clock::now();
   std::string src = kPrelude;
   for (auto& k : job->kernels) {
-    src += "extern \"C\" __global__ void __launch_bounds__(256) ";
+    // the text names its kernel kNamePlaceholder
+    const size_t at = k.second.find(kNamePlaceholder);
+    src += k.second.substr(0, at);
     src += k.first;
-    src += k.second;
+    src += k.second.substr(at + strlen(kNamePlaceholder));
   }
   const char* dump = getenv("QS_JIT_DUMP");
   if (dump && *dump) {
