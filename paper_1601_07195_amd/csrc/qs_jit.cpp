@@ -493,160 +493,34 @@ class PassEmitter {
     src_("    }");
   }
 
-  // End of the run of uncontrolled diagonal ops that starts at op i (at
-  // least i + 1).
-  int diag_run_end(int i) const {
-    int j = i;
-    while (j < p_.op_first + p_.nops && (plan_.ops[j].kind & 255) == kOpDiag && (plan_.ops[j].ctl >> 8) == kNoBit)
-      ++j;
+  // Whether op i can join a diagonal block: a diagonal op whose control (if
+  // any) is not a register bit, or a phase run (with its entries).
+  bool block_op(int i) const {
+    const int k = plan_.ops[i].kind & 255;
+    if (k == kOpPhaseRun) return true;
+    return k == kOpDiag && (plan_.ops[i].ctl >> 8) != kInReg;
+  }
+  // Index after op i (a phase run spans its entries).
+  int op_next(int i) const {
+    const FOp& op = plan_.ops[i];
+    return (op.kind & 255) == kOpPhaseRun ? i + op.aux + 1 : i + 1;
+  }
+  // End of the diagonal block that starts at op i, and its number of ops.
+  int diag_block_end(int i, int* count) const {
+    int j = i, c = 0;
+    while (j < p_.op_first + p_.nops && block_op(j)) {
+      j = op_next(j);
+      ++c;
+    }
+    *count = c;
     return j;
   }
 
-  // Uncontrolled diagonal ops [i0, i1) in one go.  Diagonal unitaries
-  // commute, so the run's product is one factor per amplitude:
-  //   F(r) = T * prod_k A_k[bit k of r],
-  // T the product of the factors of ops whose target is a thread bit or
-  // outside the tile (one value per thread), A_k[b] the product of d_b over
-  // the ops on register bit k.  F is built over the register bits as a
-  // product tree and each amplitude is scaled once.  In the adjoint the
-  // gradient terms Im(conj(lambda_r) psi_r) are unchanged by a diagonal
-  // unitary applied to both tiles, so they are formed once for the run and
-  // each op's gradient is a signed sum of them.
-  void emit_diag_run(int i0, int i1) {
-    src_("    {  // ops %d-%d: %d uncontrolled diagonal ops", i0 - p_.op_first, i1 - 1 - p_.op_first, i1 - i0);
-    bool grad = false, grad_thr = false;
-    for (int i = i0; i < i1; ++i) {
-      const FOp& op = plan_.ops[i];
-      if (adj_ && op.aux >= 0) {
-        grad = true;
-        if ((op.tgt >> 8) != kInReg) grad_thr = true;
-      }
-    }
-    // complex64 keeps the terms (each costs four conversions to double);
-    // complex128 forms them again per op (two instructions each), which
-    // keeps fewer registers live
-    const bool keep = g_.c64;
-    auto term = [&](int r) {
-      char b[96];
-      if (keep)
-        snprintf(b, sizeof b, "w%d_", r);
-      else
-        snprintf(b, sizeof b, "QS_IMC(yr[%d], yi[%d], xr[%d], xi[%d])", r, r, r, r);
-      return std::string(b);
-    };
-    if (grad) {
-      if (keep)
-        for (int r = 0; r < g_.RA; ++r)
-          src_("      const double w%d_ = QS_IMC(yr[%d], yi[%d], xr[%d], xi[%d]);", r, r, r, r, r);
-      if (grad_thr) {
-        src_("      double wt_ = 0.0;");
-        for (int r = 0; r < g_.RA; ++r) src_("      wt_ += %s;", term(r).c_str());
-      }
-      for (int i = i0; i < i1; ++i) {
-        const FOp& op = plan_.ops[i];
-        if (op.aux < 0) continue;
-        const int tw = op.tgt >> 8, tix = op.tgt & 255;
-        src_("      {  // op %d: gradient, target %d/%d", i - p_.op_first, tw, tix);
-        if (tw == kInReg) {
-          src_("      double g_ = 0.0;");
-          for (int r = 0; r < g_.RA; ++r) src_("      g_ %s= %s;", ((r >> tix) & 1) ? "-" : "+", term(r).c_str());
-        } else {
-          src_("      double g_ = %s ? -wt_ : wt_;",
-               tw == kInThread ? thread_bit(tix).c_str() : outside_bit(tix).c_str());
-        }
-        emit_grad_store(op.aux);
-        src_("      }");
-      }
-    }
-    // T and the per-register-bit products; "one" marks a factor known to be 1
-    bool t_one = true;
-    for (int i = i0; i < i1; ++i)
-      if ((plan_.ops[i].tgt >> 8) != kInReg) {
-        src_("      R tr_, ti_;");
-        break;
-      }
-    std::vector<int> a_have(g_.nreg, 0);   // any op on register bit k
-    std::vector<int> a0_one(g_.nreg, 1);   // A_k[0] still 1 (phase ops only)
-    for (int i = i0; i < i1; ++i) {
-      const FOp& op = plan_.ops[i];
-      const int tw = op.tgt >> 8, tix = op.tgt & 255;
-      const bool phase = op.m[0] == 1.0 && op.m[1] == 0.0;
-      const int j = i - p_.op_first;
-      src_("      const double* m%d_ = %s->m;", j, opref(i).c_str());
-      if (tw == kInReg) {
-        if (!a_have[tix]) {
-          src_("      R a%d1r = (R)m%d_[6], a%d1i = (R)m%d_[7];", tix, j, tix, j);
-        } else {
-          src_("      QS_CMUL(a%d1r, a%d1i, (R)m%d_[6], (R)m%d_[7])", tix, tix, j, j);
-        }
-        if (!phase) {
-          if (a0_one[tix])
-            src_("      R a%d0r = (R)m%d_[0], a%d0i = (R)m%d_[1];", tix, j, tix, j);
-          else
-            src_("      QS_CMUL(a%d0r, a%d0i, (R)m%d_[0], (R)m%d_[1])", tix, tix, j, j);
-          a0_one[tix] = 0;
-        }
-        a_have[tix] = 1;
-      } else {
-        const std::string b = tw == kInThread ? thread_bit(tix) : outside_bit(tix);
-        src_("      {");
-        src_("        const bool s_ = %s;", b.c_str());
-        src_("        const R fr_ = s_ ? (R)m%d_[6] : (R)m%d_[0], fi_ = s_ ? (R)m%d_[7] : (R)m%d_[1];", j, j, j, j);
-        if (t_one)
-          src_("        tr_ = fr_; ti_ = fi_;");
-        else
-          src_("        QS_CMUL(tr_, ti_, fr_, fi_)");
-        src_("      }");
-        t_one = false;
-      }
-    }
-    // F over the registers: level k doubles the list with A_k
-    std::vector<std::string> fr(1, t_one ? "" : "tr_"), fi(1, t_one ? "" : "ti_");
-    int nf = 0;
-    for (int k = 0; k < g_.nreg; ++k) {
-      const int m = (int)fr.size();
-      std::vector<std::string> nr(2 * m), ni(2 * m);
-      for (int r = 0; r < m; ++r)
-        for (int b = 0; b < 2; ++b) {
-          const int o = r + b * m;
-          const bool a_one = !a_have[k] || (b == 0 && a0_one[k]);
-          char ar[16], ai[16];
-          snprintf(ar, sizeof ar, "a%d%dr", k, b);
-          snprintf(ai, sizeof ai, "a%d%di", k, b);
-          if (a_one) {
-            nr[o] = fr[r];
-            ni[o] = fi[r];
-          } else if (fr[r].empty()) {
-            nr[o] = ar;
-            ni[o] = ai;
-          } else {
-            char v[16];
-            snprintf(v, sizeof v, "f%d", nf++);
-            src_("      const R %sr = %s * %s - %s * %s, %si = %s * %s + %s * %s;", v, fr[r].c_str(), ar,
-                 fi[r].c_str(), ai, v, fr[r].c_str(), ai, fi[r].c_str(), ar);
-            nr[o] = std::string(v) + "r";
-            ni[o] = std::string(v) + "i";
-          }
-        }
-      fr.swap(nr);
-      fi.swap(ni);
-    }
-    // the list is indexed with register bit k at position k: entry
-    // r + b * 2^k at level k
-    for (int r = 0; r < g_.RA; ++r) {
-      if (fr[r].empty()) continue;
-      src_("      QS_SC(xr, xi, %d, %s, %s)", r, fr[r].c_str(), fi[r].c_str());
-      if (adj_) src_("      QS_SC(yr, yi, %d, %s, %s)", r, fr[r].c_str(), fi[r].c_str());
-    }
-    src_("    }");
-  }
-
-  // A phase run (forward passes only): per-lane product of the run's
-  // phases, then the target-bit-1 amplitudes scaled once.
-  int emit_run(int i) {
+  // The per-lane factor (pr, pi) of the phase run at op i: the product of
+  // its entries' phases (explicit entries, the per-thread table and the
+  // tile-index tables).
+  void emit_run_factor(int i) {
     const FOp& h = plan_.ops[i];
-    const int tw = h.tgt >> 8, tix = h.tgt & 255;
-    src_("    {  // op %d: phase run of %d explicit entries, target %d/%d", i - p_.op_first, h.aux, tw, tix);
     src_("      const QsOp* h_ = %s;", opref(i).c_str());
     if (h.m[4] != 0.0) {
       src_("      R pr = ttr%d, pi = tti%d;", i - p_.op_first, i - p_.op_first);
@@ -678,6 +552,200 @@ class PassEmitter {
       src_("        QS_CMUL(pr, pi, (R)thi[2 * hi], (R)thi[2 * hi + 1])");
       src_("      }");
     }
+  }
+
+  // A block of diagonal ops [i0, i1) in one go.  Diagonal unitaries
+  // commute, so the block's product is one factor per amplitude:
+  //   F(r) = T * prod_k A_k[bit k of r],
+  // T the product of the factors of ops whose target is a thread bit or
+  // outside the tile (one value per lane), A_k[b] the product of the
+  // factors on register bit k where that bit is b (a control on a thread
+  // bit or outside the tile selects 1 where it is 0).  F is built over the
+  // register bits as a product tree and each amplitude is scaled once.  In
+  // the adjoint the gradient terms Im(conj(lambda_r) psi_r) are unchanged by
+  // a diagonal unitary applied to both tiles, so they are formed once for
+  // the block and each rotation's gradient is a signed sum of them.
+  void emit_diag_block(int i0, int i1) {
+    src_("    {  // ops %d-%d: diagonal block", i0 - p_.op_first, i1 - 1 - p_.op_first);
+    bool grad = false, grad_thr = false, any_thr = false;
+    for (int i = i0; i < i1; i = op_next(i)) {
+      const FOp& op = plan_.ops[i];
+      if ((op.tgt >> 8) != kInReg) any_thr = true;
+      if (adj_ && (op.kind & 255) == kOpDiag && op.aux >= 0) {
+        grad = true;
+        if ((op.tgt >> 8) != kInReg) grad_thr = true;
+      }
+    }
+    // complex64 keeps the terms (each costs four conversions to double);
+    // complex128 forms them again per op (two instructions each), which
+    // keeps fewer registers live
+    const bool keep = g_.c64;
+    auto term = [&](int r) {
+      char b[96];
+      if (keep)
+        snprintf(b, sizeof b, "w%d_", r);
+      else
+        snprintf(b, sizeof b, "QS_IMC(yr[%d], yi[%d], xr[%d], xi[%d])", r, r, r, r);
+      return std::string(b);
+    };
+    if (grad) {
+      if (keep)
+        for (int r = 0; r < g_.RA; ++r)
+          src_("      const double w%d_ = QS_IMC(yr[%d], yi[%d], xr[%d], xi[%d]);", r, r, r, r, r);
+      if (grad_thr) {
+        src_("      double wt_ = 0.0;");
+        for (int r = 0; r < g_.RA; ++r) src_("      wt_ += %s;", term(r).c_str());
+      }
+      for (int i = i0; i < i1; i = op_next(i)) {
+        const FOp& op = plan_.ops[i];
+        if ((op.kind & 255) != kOpDiag || op.aux < 0) continue;
+        const int tw = op.tgt >> 8, tix = op.tgt & 255;
+        src_("      {  // op %d: gradient, target %d/%d", i - p_.op_first, tw, tix);
+        if (tw == kInReg) {
+          src_("      double g_ = 0.0;");
+          for (int r = 0; r < g_.RA; ++r) src_("      g_ %s= %s;", ((r >> tix) & 1) ? "-" : "+", term(r).c_str());
+        } else {
+          src_("      double g_ = %s ? -wt_ : wt_;",
+               tw == kInThread ? thread_bit(tix).c_str() : outside_bit(tix).c_str());
+        }
+        emit_grad_store(op.aux);
+        src_("      }");
+      }
+    }
+    // T and the per-register-bit products
+    if (any_thr) src_("      R tr_, ti_;");
+    bool t_one = true;                     // T still 1
+    std::vector<int> a1_one(g_.nreg, 1);   // A_k[1] still 1
+    std::vector<int> a0_one(g_.nreg, 1);   // A_k[0] still 1
+    // multiply (vr, vi) into factor `name` (declared on first use)
+    auto mul_into = [&](const std::string& name, bool* one, const std::string& vr, const std::string& vi) {
+      if (*one)
+        src_("      R %sr = %s, %si = %s;", name.c_str(), vr.c_str(), name.c_str(), vi.c_str());
+      else
+        src_("      QS_CMUL(%sr, %si, %s, %s)", name.c_str(), name.c_str(), vr.c_str(), vi.c_str());
+      *one = false;
+    };
+    for (int i = i0; i < i1; i = op_next(i)) {
+      const FOp& op = plan_.ops[i];
+      const int j = i - p_.op_first;
+      const int tw = op.tgt >> 8, tix = op.tgt & 255;
+      std::string f1r, f1i, f0r, f0i;  // factor where the target bit is 1 / 0 (empty: 1)
+      std::string on;                  // control condition (empty: none)
+      if ((op.kind & 255) == kOpPhaseRun) {
+        src_("      R p%dr, p%di;", j, j);
+        src_("      {  // op %d: phase run of %d explicit entries, target %d/%d", j, op.aux, tw, tix);
+        emit_run_factor(i);
+        src_("      p%dr = pr; p%di = pi;", j, j);
+        src_("      }");
+        f1r = "p" + std::to_string(j) + "r";
+        f1i = "p" + std::to_string(j) + "i";
+      } else {
+        const int cw = op.ctl >> 8, ci = op.ctl & 255;
+        const bool phase = op.m[0] == 1.0 && op.m[1] == 0.0;
+        src_("      const double* m%d_ = %s->m;  // op %d: diagonal, target %d/%d, control %d/%d%s", j,
+             opref(i).c_str(), j, tw, tix, cw, ci, phase ? ", phase" : "");
+        char b[64];
+        snprintf(b, sizeof b, "(R)m%d_[6]", j);
+        f1r = b;
+        snprintf(b, sizeof b, "(R)m%d_[7]", j);
+        f1i = b;
+        if (!phase) {
+          snprintf(b, sizeof b, "(R)m%d_[0]", j);
+          f0r = b;
+          snprintf(b, sizeof b, "(R)m%d_[1]", j);
+          f0i = b;
+        }
+        if (cw != kNoBit) on = cw == kInThread ? thread_bit(ci) : outside_bit(ci);
+      }
+      if (tw == kInReg) {
+        auto put = [&](int bit, const std::string& fr, const std::string& fi) {
+          if (fr.empty()) return;
+          char nm[16];
+          snprintf(nm, sizeof nm, "a%d%d", tix, bit);
+          std::vector<int>& one = bit ? a1_one : a0_one;
+          bool o = one[tix];
+          if (on.empty()) {
+            mul_into(nm, &o, fr, fi);
+          } else {
+            src_("      const bool c%d%d_ = %s;", j, bit, on.c_str());
+            char sr[96], si[96];
+            snprintf(sr, sizeof sr, "(c%d%d_ ? %s : (R)1)", j, bit, fr.c_str());
+            snprintf(si, sizeof si, "(c%d%d_ ? %s : (R)0)", j, bit, fi.c_str());
+            mul_into(nm, &o, sr, si);
+          }
+          one[tix] = o;
+        };
+        put(1, f1r, f1i);
+        put(0, f0r, f0i);
+      } else {
+        const std::string tb = tw == kInThread ? thread_bit(tix) : outside_bit(tix);
+        src_("      {");
+        src_("        const bool s_ = %s;", tb.c_str());
+        std::string c = on.empty() ? "" : on;
+        const std::string fr0 = f0r.empty() ? "(R)1" : f0r, fi0 = f0i.empty() ? "(R)0" : f0i;
+        if (c.empty()) {
+          src_("        const R fr_ = s_ ? %s : %s, fi_ = s_ ? %s : %s;", f1r.c_str(), fr0.c_str(), f1i.c_str(),
+               fi0.c_str());
+        } else {
+          src_("        const bool on_ = %s;", c.c_str());
+          src_("        const R fr_ = on_ ? (s_ ? %s : %s) : (R)1, fi_ = on_ ? (s_ ? %s : %s) : (R)0;", f1r.c_str(),
+               fr0.c_str(), f1i.c_str(), fi0.c_str());
+        }
+        if (t_one)
+          src_("        tr_ = fr_; ti_ = fi_;");
+        else
+          src_("        QS_CMUL(tr_, ti_, fr_, fi_)");
+        src_("      }");
+        t_one = false;
+      }
+    }
+    // F over the registers: level k doubles the list with A_k
+    std::vector<std::string> fr(1, t_one ? "" : "tr_"), fi(1, t_one ? "" : "ti_");
+    int nf = 0;
+    for (int k = 0; k < g_.nreg; ++k) {
+      const int m = (int)fr.size();
+      std::vector<std::string> nr(2 * m), ni(2 * m);
+      for (int r = 0; r < m; ++r)
+        for (int bb = 0; bb < 2; ++bb) {
+          const int o = r + bb * m;
+          const bool a_one = bb ? a1_one[k] : a0_one[k];
+          char ar[16], ai[16];
+          snprintf(ar, sizeof ar, "a%d%dr", k, bb);
+          snprintf(ai, sizeof ai, "a%d%di", k, bb);
+          if (a_one) {
+            nr[o] = fr[r];
+            ni[o] = fi[r];
+          } else if (fr[r].empty()) {
+            nr[o] = ar;
+            ni[o] = ai;
+          } else {
+            char v[16];
+            snprintf(v, sizeof v, "f%d", nf++);
+            src_("      const R %sr = %s * %s - %s * %s, %si = %s * %s + %s * %s;", v, fr[r].c_str(), ar,
+                 fi[r].c_str(), ai, v, fr[r].c_str(), ai, fi[r].c_str(), ar);
+            nr[o] = std::string(v) + "r";
+            ni[o] = std::string(v) + "i";
+          }
+        }
+      fr.swap(nr);
+      fi.swap(ni);
+    }
+    // entry r + b * 2^k of level k: register bit k of r is b
+    for (int r = 0; r < g_.RA; ++r) {
+      if (fr[r].empty()) continue;
+      src_("      QS_SC(xr, xi, %d, %s, %s)", r, fr[r].c_str(), fi[r].c_str());
+      if (adj_) src_("      QS_SC(yr, yi, %d, %s, %s)", r, fr[r].c_str(), fi[r].c_str());
+    }
+    src_("    }");
+  }
+
+  // A phase run (forward passes only): per-lane product of the run's
+  // phases, then the target-bit-1 amplitudes scaled once.
+  int emit_run(int i) {
+    const FOp& h = plan_.ops[i];
+    const int tw = h.tgt >> 8, tix = h.tgt & 255;
+    src_("    {  // op %d: phase run of %d explicit entries, target %d/%d", i - p_.op_first, h.aux, tw, tix);
+    emit_run_factor(i);
     if (tw == kInReg) {
       for (int r = 0; r < g_.RA; ++r)
         if ((r >> tix) & 1) src_("      QS_SC(xr, xi, %d, pr, pi)", r);
@@ -756,11 +824,12 @@ class PassEmitter {
     for (int i = p_.op_first; i < p_.op_first + p_.nops; ++i) {
       const FOp& op = plan_.ops[i];
       const int kind = op.kind & 255;
-      // a run of uncontrolled diagonal ops is emitted as one op
-      const int run_end = kind == kOpDiag ? diag_run_end(i) : i + 1;
-      const bool diag_run = run_end - i >= 2;
-      const int next = kind == kOpPhaseRun ? i + op.aux + 1 : diag_run ? run_end : i + 1;
-      release_upto(diag_run ? run_end - 1 : i);
+      // a block of two or more diagonal ops is emitted as one
+      int nblk = 0;
+      const int blk_end = block_op(i) ? diag_block_end(i, &nblk) : i + 1;
+      const bool blk = nblk >= 2;
+      const int next = blk ? blk_end : kind == kOpPhaseRun ? i + op.aux + 1 : i + 1;
+      release_upto(blk ? blk_end - 1 : i);
       // the next op that reads a record
       for (int j = next; j < p_.op_first + p_.nops; ++j) {
         const int k = plan_.ops[j].kind & 255;
@@ -776,9 +845,9 @@ class PassEmitter {
         if (adj_) emit_remap_tile("yr", "yi", op.aux, op.tgt);
       } else if (kind == kOpU) {
         emit_u(i);
-      } else if (kind == kOpDiag && diag_run) {
-        emit_diag_run(i, run_end);
-        i = run_end - 1;
+      } else if (blk) {
+        emit_diag_block(i, blk_end);
+        i = blk_end - 1;
       } else if (kind == kOpDiag) {
         emit_diag(i);
       } else if (kind == kOpPhaseRun) {
