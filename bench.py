@@ -64,11 +64,13 @@ def parse():
     ap.add_argument("--ps-pairs", type=int, default=8,
                     help="parameter-shift pairs timed at n=28 (extrapolated to all 2P sweeps)")
     ap.add_argument("--cpu-n", type=int, default=0, help="qubits of the CPU-oracle sample (0 = auto)")
-    ap.add_argument("--workload-only", choices=["circuit", "qft", "iqft", "adjoint", "batch"],
+    ap.add_argument("--workload-only", choices=["circuit", "qft", "iqft", "adjoint", "batch", "cu-line"],
                     help="run one workload once after a warmup, plus a 4 GiB STREAM copy, and exit "
                          "(for hardware-counter runs): the 1000-gate random circuit, the QFT or IQFT on "
-                         "all qubits at --n/--dtype, the n = 28 ansatz energy + gradient (--dtype), or "
-                         "the 4096-circuit batch (--dtype)")
+                         "all qubits at --n/--dtype, the n = 28 ansatz energy + gradient (--dtype), "
+                         "the 4096-circuit batch (--dtype), or controlled gates with control qubits "
+                         "0..3 and target 20 at --n/--dtype (twice each; QS_CU_COMPACT_FROM picks the "
+                         "enumeration)")
     return ap.parse_args()
 
 
@@ -93,6 +95,15 @@ def workload_only(args) -> None:
         torch.cuda.synchronize()
         log(f"[bench] {w} n={n} {args.dtype}: warmup done")
         st.run(ops)
+        torch.cuda.synchronize()
+        del st
+    elif w == "cu-line":
+        n = args.n
+        st = Q.State(n, dtype)
+        u = C.haar_unitary(np.random.default_rng(C.SEED_BASE + 9))
+        for c in range(4):
+            for _ in range(2):
+                st.apply_cu(c, 20, u)
         torch.cuda.synchronize()
         del st
     elif w == "adjoint":

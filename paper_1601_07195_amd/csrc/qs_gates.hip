@@ -34,6 +34,7 @@
 // when each XCD walks one contiguous eighth of the work ("XCD-contiguous"
 // order), which the dispatch rules below select from a measured sweep.
 #include <algorithm>
+#include <cstdlib>
 
 #include "qs_device.h"
 #include "qs_internal.h"
@@ -275,10 +276,34 @@ static void units_1q(StateImpl* s, int u, int t, const Mat<R>& q) {
   else go_pair<R, T, kNone, 0>(s, 1ull << (u - 1), t, 0, q);
 }
 
+// QS_CU_COMPACT_FROM (0..3), when set, is the lowest control unit bit that
+// takes the compact enumeration, replacing the rule below; it exists to
+// measure the compact pass over control-1 runs shorter than a line against
+// the predicated one.
+static int compact_from_env() {
+  const char* e = getenv("QS_CU_COMPACT_FROM");
+  if (!e || !*e) return -1;
+  const int x = atoi(e);
+  return x < 0 ? 0 : x > kLineUnitBits ? kLineUnitBits : x;
+}
+
+// Whether a controlled gate with control unit bit c and target unit bit t
+// takes the compact enumeration.  From a full 128-byte line of control-1
+// units up it always does (half the traffic).  Below the line the memory
+// side still fetches whole lines, so the compact pass moves as many read
+// bytes as the predicated one; with 64-byte runs (unit bit 2) it writes
+// half and measured 7-12 % faster for target unit bits 12-23, slower or
+// equal elsewhere; with 16- or 32-byte runs it is a third slower.
+static bool cu_compact(int c, int t) {
+  const int from = compact_from_env();
+  if (from >= 0) return c >= from;
+  return c >= kLineUnitBits || (c == kLineUnitBits - 1 && t >= 12 && t <= 23);
+}
+
 // Controlled gate, control unit bit c, target unit bit t, 2^u units.
 template <typename R, typename T>
 static void units_cu(StateImpl* s, int u, int c, int t, const Mat<R>& q) {
-  const bool compact = c >= kLineUnitBits;
+  const bool compact = cu_compact(c, t);
   if (t < kExchangeBits) {
     if (compact) go_exchange<R, T, kCompact>(s, 1ull << (u - 1), t < c ? t : t - 1, c, q);
     else go_exchange<R, T, kPred>(s, 1ull << u, t, c, q);
@@ -330,7 +355,7 @@ Status launch_apply_cu(StateImpl* s, int c, int t, const double* q) {
   const int u = n - 1;
   if (t == 0) {  // pair inside each unit; control unit bit c - 1
     const int cv = c - 1;
-    if (cv >= kLineUnitBits) go_inner<kCompact>(s, 1ull << (u - 1), cv, m);
+    if (cu_compact(cv, 0)) go_inner<kCompact>(s, 1ull << (u - 1), cv, m);
     else go_inner<kPred>(s, 1ull << u, cv, m);
   } else if (c == 0) {  // control inside each unit: update odd amplitudes only
     const int tv = t - 1;

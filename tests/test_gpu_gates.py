@@ -100,6 +100,29 @@ def test_cu_sampled_pairs_ragged_sizes(Q, name):
                 ref = rounded_input(got, True)
 
 
+@pytest.mark.parametrize("name", DTYPES)
+def test_cu_compact_below_the_line(Q, name, monkeypatch):
+    """QS_CU_COMPACT_FROM=0 sends controls inside a 128-byte line to the
+    compact enumeration too (the measurement of the line granularity uses
+    it): every pair at n = 9 and sampled pairs at n = 13 against the oracle."""
+    monkeypatch.setenv("QS_CU_COMPACT_FROM", "0")  # every control bit
+    rng = np.random.default_rng(350)
+    for n in (9, 13):
+        psi = random_state(n, rng)
+        st = to_gpu_state(Q, psi, dt(Q, name))
+        ref = rounded_input(psi, name == "c64")
+        pairs = [(c, t) for c in range(n) for t in range(n) if c != t] if n == 9 else \
+            [(0, 12), (1, 12), (2, 12), (3, 9), (1, 0), (2, 5), (0, 1), (3, 2)]
+        for c, t in pairs:
+            u = C.haar_unitary(rng)
+            st.apply_cu(c, t, u)
+            O.apply_cu(ref, n, c, t, u)
+            got = st.numpy()
+            assert np.abs(got - ref).max() <= tol(name), (n, c, t)
+            if name == "c64":
+                ref = rounded_input(got, True)
+
+
 def test_cnot_exact_permutation_on_gpu(Q):
     n = 12
     psi = random_state(n, np.random.default_rng(7))
