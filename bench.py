@@ -161,15 +161,18 @@ class EventTimer:
         return out
 
 
-def measured_traffic(kernel: str, workload: str):
+def measured_traffic(kernel: str, workload: str, key: str = ""):
     """HBM bytes per launch of `kernel` on `workload` from the rocprofv3 PMC
     summary committed under profiles/ (FETCH_SIZE and WRITE_SIZE, scaled by
     the same counters on the STREAM-copy kernel), or None when there is no
-    such summary or the kernel's source has changed since it was taken."""
+    such summary or the kernel's source has changed since it was taken.  A
+    summary of several workloads holds one `traffic_bytes_per_launch.<key>`
+    line per workload."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
     if not os.path.exists(path):
         return None
+    want = "traffic_bytes_per_launch" + (f".{key}" if key else "")
     fields = {}
     for line in open(path):
         if ":" in line and line.startswith(("traffic_bytes_per_launch", "source_file", "source_sha256")):
@@ -181,9 +184,54 @@ def measured_traffic(kernel: str, workload: str):
             h.update(open(os.path.join(ROOT, f.strip()), "rb").read())
         if h.hexdigest() != fields["source_sha256"]:
             return None
-        return float(fields["traffic_bytes_per_launch"])
+        return float(fields[want])
     except (KeyError, OSError, ValueError):
         return None
+
+
+# LDS peak for the batch kernel's roofline: 128 bytes per clock per CU
+# (one 128-byte LDS access per clock), 256 CUs at 2.4 GHz.
+PEAK_LDS_GBPS = 128 * 256 * 2.4
+
+
+def section_rooflines(line):
+    """Rooflines of the kernels the sections after the main step time: the
+    QFT / IQFT passes (phase runs) at n = 30 complex128 and n = 31 complex64,
+    the adjoint's forward and reverse passes at n = 28, and the batch kernel
+    (LDS-bound: its modelled LDS bytes against the LDS peak)."""
+    out = {}
+
+    def put(name, launches, nbytes, ms, traffic, bound="hbm", peak=PEAK_HBM_GBPS):
+        gbps = nbytes / (ms * 1e-3) / 1e9
+        out[name] = {"bound": bound, "launches_per_step": launches, "bytes_per_launch": nbytes,
+                     "mean_launch_ms": round(ms, 4), "achieved_GBps": round(gbps, 1), "peak_GBps": round(peak, 1),
+                     "frac": round(gbps / peak, 4), "traffic": traffic}
+
+    q = line.get("qft_fused_vs_unfused") or {}
+    for dt, n, b in (("c128", 30, 16), ("c64", 31, 8)):
+        rows = q.get(dt, {}).get(str(n))
+        if not rows:
+            continue
+        for kind in ("qft", "iqft"):
+            r = rows[kind]
+            put(f"qs_pass_* ({kind.upper()} phase runs, n={n} {dt})", r["passes_fused"], 2 * (1 << n) * b,
+                r["fused_s"] / r["passes_fused"] * 1e3,
+                measured_traffic("qs_pass_compiled_phase_runs", "qft_iqft", f"{kind}_{dt}_n{n}"))
+    adj = (line.get("adjoint_vs_param_shift") or {}).get("n28", {}).get("sweeps", {})
+    for dt, b in (("c128", 16), ("c64", 8)):
+        sw = adj.get(dt)
+        if not sw:
+            continue
+        S = (1 << 28) * b
+        put(f"qs_pass_* (adjoint forward sweep, n=28 {dt})", sw["forward_passes"], 2 * S, sw["forward_pass_ms"],
+            measured_traffic("qs_pass_compiled_adjoint", "n28", f"forward_{dt}"))
+        put(f"qs_pass_* (adjoint reverse sweep, n=28 {dt})", sw["reverse_passes"], 4 * S, sw["reverse_pass_ms"],
+            measured_traffic("qs_pass_compiled_adjoint", "n28", f"reverse_{dt}"))
+    bt = (line.get("batch") or {}).get("c128")
+    if bt:
+        put("k_batch (4096 circuits, c128)", 1, bt["lds_bytes_model"], bt["batch_s"] * 1e3, None,
+            bound="lds", peak=PEAK_LDS_GBPS)
+    return out
 
 
 def cpu_baseline(n_gpu: int, u, pairs, args):
@@ -589,6 +637,14 @@ def adjoint_section(Q, C, np, torch, ps_pairs):
             e64, g64 = adj64()
         rec["c64_adjoint_s"] = round((time.perf_counter() - t0) / reps, 4)
         if n == 28:
+            # the two sweeps apart, for per-pass rooflines
+            s128 = Q.State(n, Q.QS_C128, stream=stream)
+            l128 = Q.State(n, Q.QS_C128, stream=stream, init=False)
+            rec["sweeps"] = {
+                "c128": sweep_split(Q, torch, np, n, circ, x, z, ham.coeff, Q.QS_C128, s128, l128, stream),
+                "c64": sweep_split(Q, torch, np, n, circ, x, z, ham.coeff, Q.QS_C64, s64, l64, stream)}
+            del s128, l128
+            torch.cuda.empty_cache()
             # both sweeps on wide tiles (fewer passes), complex128 and complex64
             for nm, s_, l_ in (("c128", None, None), ("c64", s64, l64)):
                 if s_ is None:
@@ -616,6 +672,43 @@ def adjoint_section(Q, C, np, torch, ps_pairs):
             rec["error_vs_fp64_oracle"] = oracle_errors(C, np, circ, ham, n, {"c128": (e, g), "c64": (e64, g64)})
         out[f"n{n}"] = rec
     return out
+
+
+def sweep_split(Q, torch, np, n, circ, x, z, coeff, dtype, st, lam, stream, reps=3):
+    """The adjoint's forward sweep (a fused run of the circuit), lambda = H psi
+    alone, and H psi + energy + reverse sweep (QS_ADJ_STATE_IS_FINAL on the
+    final state), each timed; the reverse sweep is the last minus H psi.
+    Per-pass times against 2S (forward) and 4S (reverse, psi and lambda)."""
+    S = (1 << n) * (16 if dtype == Q.QS_C128 else 8)
+    fwd, _, _ = Q.qs_plan(n, dtype, circ.ops, circ.theta)
+    rev, _, _ = Q.qs_plan(n, dtype, circ.ops, circ.theta, flags=Q.QS_PLAN_ADJOINT_REVERSE)
+    tf, th, tr = [], [], []
+    for i in range(reps + 1):
+        st.init_basis(0)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e2 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        st.run(circ.ops, circ.theta)
+        e1.record(stream)
+        Q.qs_apply_pauli_sum(st.handle, lam.handle, x, z, coeff)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Q.qs_grad_adjoint(st.handle, circ.ops, circ.theta, x, z, coeff, lam.handle, Q.QS_ADJ_STATE_IS_FINAL)
+        t1 = time.perf_counter()
+        if i > 0:  # the first round compiles
+            tf.append(e0.elapsed_time(e1) * 1e-3)
+            th.append(e1.elapsed_time(e2) * 1e-3)
+            tr.append(t1 - t0)
+    f_s, h_s, fin_s = (float(np.median(v)) for v in (tf, th, tr))
+    r_s = fin_s - h_s
+    fp, rp = f_s / fwd["passes"], r_s / rev["passes"]
+    return {"forward_passes": fwd["passes"], "forward_s": round(f_s, 4), "forward_pass_ms": round(fp * 1e3, 4),
+            "forward_pass_frac": round(2 * S / fp / 1e9 / PEAK_HBM_GBPS, 4),
+            "h_psi_s": round(h_s, 4), "final_state_adjoint_s": round(fin_s, 4),
+            "reverse_passes": rev["passes"], "reverse_s": round(r_s, 4), "reverse_pass_ms": round(rp * 1e3, 4),
+            "reverse_pass_frac": round(4 * S / rp / 1e9 / PEAK_HBM_GBPS, 4)}
 
 
 def oracle_errors(C, np, circ, ham, n, results, nsample=8):
@@ -851,8 +944,12 @@ def main():
     # duration divided by its launches (all fused for this circuit).
     n_sweep = len(one_q) / args.steps
     circ_med = statistics.median(circ_t)
+    # fused passes run compiled per pass shape from n = 26 (the library's
+    # automatic choice), on the interpreter kernels below that
+    fused_name = ("qs_pass_* (fused pass compiled for its shape, circuit)" if n >= 26
+                  else "k_fused (interpreted fused pass, circuit)")
     kernels = {
-        "k_fused (fused pass, circuit)": {
+        fused_name: {
             "launches_per_step": plan_info["passes"], "bytes_per_launch": 2 * S,
             "mean_launch_ms": circ_med / plan_info["passes"] * 1e3,
             "step_s": circ_med},
@@ -876,7 +973,7 @@ def main():
         v["step_s"] = round(v["step_s"], 4)
     dom = max(kernels, key=lambda k: kernels[k]["step_s"])
     traffic = None
-    if dom.startswith("k_fused"):
+    if dom.startswith("qs_pass_*"):  # the compiled passes' summary
         traffic = measured_traffic(f"qs_pass_compiled_circuit_{args.dtype}", f"n{n}")
     roof = {"kernel": dom, "bound": "hbm", "achieved": kernels[dom]["achieved_GBps"],
             "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": kernels[dom]["frac"], "traffic": traffic,
@@ -951,6 +1048,7 @@ def main():
         "programs_clang": js["programs_clang"], "programs_hiprtc": js["programs_hiprtc"],
         "note": "fused passes at n >= 26 run kernels compiled per pass shape; compiled during warmup "
                 "and the untimed first call of each section, never inside a timed region"}
+    line["roofline_by_kernel"].update(section_rooflines(line))
     line["precision_summary"] = precision_summary(line)
     line["per_gate_summary"] = per_gate_summary(line, n, args.dtype, S)
     print(json.dumps(line), flush=True)

@@ -433,10 +433,17 @@ int qs_grad_adjoint(qs_state* s, const qs_op* ops, int nops,
  *   order    host, nops int32 or NULL: gate indices in execution order
  *            (gates only move past gates they commute with)
  *   pass_of  host, nops int32 or NULL: the pass that applies each gate
+ *   flags    QS_RUN_NO_FUSION, QS_RUN_WIDE_TILES, or QS_PLAN_ADJOINT_REVERSE
  * hbm_bytes counts algorithmic HBM traffic as Table 2 does: a pass that
  * rewrites the state moves 2 * 2^n * b bytes, a controlled gate run alone
  * 2^n * b (b = bytes per amplitude).
  */
+/* Plan the reverse sweep of qs_grad_adjoint instead (the list reversed, each
+ * gate replaced by its inverse, one gradient slot per rotation; with
+ * QS_RUN_WIDE_TILES as under QS_ADJ_WIDE_TILES): every pass moves psi and
+ * lambda, 4 * 2^n * b bytes; order and pass_of index the reversed list
+ * (entry j is input gate nops - 1 - j).  Not with QS_RUN_NO_FUSION. */
+#define QS_PLAN_ADJOINT_REVERSE 16
 typedef struct qs_plan_info {
   int32_t passes;       /* passes over the state in total */
   int32_t fused;        /* passes applying several gates in one round trip */

@@ -583,13 +583,25 @@ int qs_plan(int n, int dtype, const qs_op* ops, int nops, const double* theta, i
   if (n < 1 || n > max_qubits(dtype)) return fail(QS_ERANGE, "qs_plan: n out of range");
   if (nops < 0 || (nops > 0 && !ops)) return fail(QS_EINVAL, "qs_plan: bad op list");
   if (nparams < 0) return fail(QS_EINVAL, "qs_plan: nparams < 0");
-  if (flags & ~(QS_RUN_NO_FUSION | QS_RUN_WIDE_TILES)) return fail(QS_EINVAL, "qs_plan: unknown flags");
+  if (flags & ~(QS_RUN_NO_FUSION | QS_RUN_WIDE_TILES | QS_PLAN_ADJOINT_REVERSE))
+    return fail(QS_EINVAL, "qs_plan: unknown flags");
+  const bool reverse = (flags & QS_PLAN_ADJOINT_REVERSE) != 0;
+  if (reverse && (flags & QS_RUN_NO_FUSION))
+    return fail(QS_EINVAL, "qs_plan: QS_PLAN_ADJOINT_REVERSE with QS_RUN_NO_FUSION");
   std::vector<qs::XGate> gates;
   Status st = qs::normalize_ops(n, ops, nops, theta, nparams, &gates);
   if (!st.good()) return done(st);
   qs::Plan plan;
-  qs::plan_gates(n, dtype, gates, !(flags & QS_RUN_NO_FUSION), &plan, true, 1 << 30, false,
-                 (flags & QS_RUN_WIDE_TILES) != 0);
+  const bool wide = (flags & QS_RUN_WIDE_TILES) != 0;
+  if (reverse) {
+    // as the adjoint's reverse sweep plans it
+    std::vector<qs::XGate> rev;
+    qs::reverse_daggered(gates, &rev);
+    qs::plan_gates(n, dtype, rev, true, &plan, /*allow_single=*/false, qs::kAdjMaxSlots, /*grad=*/true, wide);
+  } else {
+    qs::plan_gates(n, dtype, gates, !(flags & QS_RUN_NO_FUSION), &plan, true, 1 << 30, false, wide);
+  }
+  const double tiles = reverse ? 2.0 : 1.0;  // psi and lambda in the reverse sweep
   if (info) {
     memset(info, 0, sizeof(*info));
     const double S = (double)((size_t)1 << n) * (double)qs::amp_bytes(dtype);
@@ -599,13 +611,13 @@ int qs_plan(int n, int dtype, const qs_op* ops, int nops, const double* theta, i
         ++info->fused;
         info->remaps += p.remaps;
         info->fused_ops += p.nops;
-        info->hbm_bytes += 2 * S;
+        info->hbm_bytes += tiles * 2 * S;
       } else if (p.kind == qs::kPass1q) {
         ++info->single_1q;
-        info->hbm_bytes += 2 * S;
+        info->hbm_bytes += tiles * 2 * S;
       } else {
         ++info->single_cu;
-        info->hbm_bytes += S;
+        info->hbm_bytes += tiles * S;
       }
     }
   }

@@ -27,6 +27,7 @@ QS_OP_U, QS_OP_CU, QS_OP_RX, QS_OP_RY, QS_OP_RZ = 0, 1, 2, 3, 4
 QS_RUN_NO_FUSION = 1
 QS_RUN_WIDE_TILES = 2
 QS_RUN_VERIFY = 4
+QS_PLAN_ADJOINT_REVERSE = 16
 QS_ADJ_STATE_IS_FINAL = 1
 QS_ADJ_WIDE_TILES = 2
 QS_BATCH_MAX_QUBITS = 24

@@ -149,3 +149,35 @@ def test_wide_tiles_plan_fewer_passes():
         wide, order, pass_of = Q.qs_plan(30, dt, ops, flags=Q.QS_RUN_WIDE_TILES)
         assert wide["passes"] < narrow["passes"] and wide["hbm_bytes"] < narrow["hbm_bytes"]
         assert sorted(order.tolist()) == list(range(len(ops)))
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_plan_of_the_adjoint_reverse_sweep(Q, dtype):
+    """QS_PLAN_ADJOINT_REVERSE plans the reversed, inverted list as the
+    adjoint's reverse sweep does: every pass fused, 4S per pass (psi and
+    lambda), and its order, applied to the inverted gates, undoes the
+    circuit (so each gate keeps its place relative to the gates it does not
+    commute with)."""
+    n = 15
+    dt = Q.QS_C128 if dtype == "c128" else Q.QS_C64
+    S = (1 << n) * (16 if dtype == "c128" else 8)
+    circ, _ = C.workload_ansatz(n, 4, 5, seed=6)
+    for flags in (0, Q.QS_RUN_WIDE_TILES):
+        info, order, pass_of = Q.qs_plan(n, dt, circ.ops, circ.theta, flags=flags | Q.QS_PLAN_ADJOINT_REVERSE)
+        assert info["passes"] == info["fused"] > 0
+        assert info["hbm_bytes"] == 4 * S * info["passes"]
+        assert sorted(order.tolist()) == list(range(len(circ.ops)))
+        assert np.all(np.diff(pass_of[order]) >= 0)
+        # the reversed list with each gate inverted, in the planned order
+        rev = circ.ops[::-1].copy()
+        th = circ.theta.copy()
+        for op in rev:
+            if op["param"] >= 0:
+                continue  # rotations: inverted below through theta
+            op["mat"] = C.mat_to_row(C.row_to_mat(op["mat"]).conj().T)
+        psi = _state(n, 7)
+        fwd = O.run(circ.ops, n, circ.theta, psi=psi.copy())
+        back = O.run(rev[order], n, -th, psi=fwd)
+        assert np.abs(back - psi).max() <= 1e-12
+    with pytest.raises(Q.QSError):
+        Q.qs_plan(n, dt, circ.ops, circ.theta, flags=Q.QS_PLAN_ADJOINT_REVERSE | Q.QS_RUN_NO_FUSION)
