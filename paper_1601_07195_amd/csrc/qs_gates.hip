@@ -268,11 +268,39 @@ Status launch_init_basis(StateImpl* s, uint64_t index) {
 // (and a grid of control/target pairs) at n = 30 on MI355X.
 constexpr int kExchangeBits = 8;  // target bits handled inside a 256-lane workgroup
 
+// Block order of the paired-stream kernel for a single-qubit gate on unit
+// bit t of a 2^u-unit state (units of 16 bytes: complex128 amplitudes,
+// complex64 pairs): 1 (consecutive blocks spread over the XCDs) where it
+// measured faster than the plain order.  From a sweep of every target with
+// both orders at u = 30..33, each size at both amplitude types, which
+// agreed in unit bits: u <= 30: bits 22-23; u = 31: 8, 22-23; u = 32: 8,
+// 21-23; u = 33 (128 GiB states): 17-27, where the plain order
+// loses up to 9 %.
+static int pair_block_order(int u, int t) {
+  if (u >= 33) return (t >= 17 && t <= 27) ? 1 : 0;
+  if (u == 32) return (t == 8 || (t >= 21 && t <= 23)) ? 1 : 0;
+  if (u == 31) return (t == 8 || t == 22 || t == 23) ? 1 : 0;
+  return (t == 22 || t == 23) ? 1 : 0;
+}
+
+// QS_1Q_BLOCK_ORDER (0 or 1), when set, forces the block order of the
+// paired-stream kernel for every target (to measure both); otherwise
+// pair_block_order decides.
+static int block_order_env() {
+  const char* e = getenv("QS_1Q_BLOCK_ORDER");
+  if (!e || !*e) return -1;
+  return atoi(e) ? 1 : 0;
+}
+
 // Single-qubit gate on unit bit t of a 2^u-unit state.
 template <typename R, typename T>
 static void units_1q(StateImpl* s, int u, int t, const Mat<R>& q) {
-  if (t < kExchangeBits) go_exchange<R, T, kNone>(s, 1ull << u, t, 0, q);
-  else if (t == 22 || t == 23) go_pair<R, T, kNone, 1>(s, 1ull << (u - 1), t, 0, q);
+  if (t < kExchangeBits) {
+    go_exchange<R, T, kNone>(s, 1ull << u, t, 0, q);
+    return;
+  }
+  const int forced = block_order_env();
+  if ((forced >= 0 ? forced : pair_block_order(u, t)) == 1) go_pair<R, T, kNone, 1>(s, 1ull << (u - 1), t, 0, q);
   else go_pair<R, T, kNone, 0>(s, 1ull << (u - 1), t, 0, q);
 }
 

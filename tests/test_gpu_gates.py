@@ -126,6 +126,28 @@ def test_cu_compact_below_the_line(Q, name, monkeypatch):
                 ref = rounded_input(got, True)
 
 
+@pytest.mark.parametrize("name", DTYPES)
+@pytest.mark.parametrize("order", ["0", "1"])
+def test_1q_block_orders(Q, name, order, monkeypatch):
+    """QS_1Q_BLOCK_ORDER forces either block order of the paired-stream
+    kernel (the dispatch table picks one per state size and target): every
+    target of a 14-qubit state against the oracle."""
+    monkeypatch.setenv("QS_1Q_BLOCK_ORDER", order)
+    n = 14
+    rng = np.random.default_rng(360 + int(order))
+    psi = random_state(n, rng)
+    st = to_gpu_state(Q, psi, dt(Q, name))
+    ref = rounded_input(psi, name == "c64")
+    for k in range(n):
+        u = C.haar_unitary(rng)
+        st.apply_1q(k, u)
+        O.apply_1q(ref, n, k, u)
+        got = st.numpy()
+        assert np.abs(got - ref).max() <= tol(name), k
+        if name == "c64":
+            ref = rounded_input(got, True)
+
+
 def test_cnot_exact_permutation_on_gpu(Q):
     n = 12
     psi = random_state(n, np.random.default_rng(7))
