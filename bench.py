@@ -64,13 +64,14 @@ def parse():
     ap.add_argument("--ps-pairs", type=int, default=8,
                     help="parameter-shift pairs timed at n=28 (extrapolated to all 2P sweeps)")
     ap.add_argument("--cpu-n", type=int, default=0, help="qubits of the CPU-oracle sample (0 = auto)")
-    ap.add_argument("--workload-only", choices=["circuit", "qft", "iqft", "adjoint", "batch", "cu-line"],
+    ap.add_argument("--workload-only", choices=["circuit", "qft", "iqft", "adjoint", "batch", "cu-line", "gates"],
                     help="run one workload once after a warmup, plus a 4 GiB STREAM copy, and exit "
                          "(for hardware-counter runs): the 1000-gate random circuit, the QFT or IQFT on "
                          "all qubits at --n/--dtype, the n = 28 ansatz energy + gradient (--dtype), "
                          "the 4096-circuit batch (--dtype), or controlled gates with control qubits "
                          "0..3 and target 20 at --n/--dtype (twice each; QS_CU_COMPACT_FROM picks the "
-                         "enumeration)")
+                         "enumeration), or the main step's streamed gates at --n/--dtype (H and a Haar U "
+                         "on every target, then the controlled-U pairs)")
     return ap.parse_args()
 
 
@@ -95,6 +96,17 @@ def workload_only(args) -> None:
         torch.cuda.synchronize()
         log(f"[bench] {w} n={n} {args.dtype}: warmup done")
         st.run(ops)
+        torch.cuda.synchronize()
+        del st
+    elif w == "gates":
+        n = args.n
+        u, pairs = C.workload_sweep(n, args.ncu, C.SEED_BASE + 1)
+        st = Q.State(n, dtype)
+        for k in range(n):
+            st.apply_1q(k, C.H_GATE)
+            st.apply_1q(k, u)
+        for c, t in pairs:
+            st.apply_cu(c, t, u)
         torch.cuda.synchronize()
         del st
     elif w == "cu-line":
@@ -966,15 +978,22 @@ def main():
             "launches_per_step": len(cu_reg) / args.steps, "bytes_per_launch": S,
             "mean_launch_ms": statistics.fmean(cu_reg) * 1e3,
             "step_s": statistics.fmean(cu_reg) * len(cu_reg) / args.steps}
+    # HBM traffic per launch of the streamed gates, from their counter summary
+    gkeys = {"k_exchange/k_pair (single-qubit gate, streaming)": "one_qubit",
+             "k_exchange/k_pair (controlled gate, streaming)": "cu_all",
+             "k_exchange/k_pair (controlled gate, control outside the 128-byte line)": "cu_outside_line"}
+    for k, key in gkeys.items():
+        if k in kernels:
+            kernels[k]["traffic"] = measured_traffic("k_pair_k_exchange_gates", f"{args.dtype}_n{n}", key)
     for v in kernels.values():
         v["achieved_GBps"] = round(v["bytes_per_launch"] / (v["mean_launch_ms"] * 1e-3) / 1e9, 1)
         v["frac"] = round(v["achieved_GBps"] / PEAK_HBM_GBPS, 4)
         v["mean_launch_ms"] = round(v["mean_launch_ms"], 4)
         v["step_s"] = round(v["step_s"], 4)
+    if n >= 26:  # the compiled passes' summary
+        kernels[fused_name]["traffic"] = measured_traffic(f"qs_pass_compiled_circuit_{args.dtype}", f"n{n}")
     dom = max(kernels, key=lambda k: kernels[k]["step_s"])
-    traffic = None
-    if dom.startswith("qs_pass_*"):  # the compiled passes' summary
-        traffic = measured_traffic(f"qs_pass_compiled_circuit_{args.dtype}", f"n{n}")
+    traffic = kernels[dom].get("traffic")
     roof = {"kernel": dom, "bound": "hbm", "achieved": kernels[dom]["achieved_GBps"],
             "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": kernels[dom]["frac"], "traffic": traffic,
             "bytes_per_launch": kernels[dom]["bytes_per_launch"],
