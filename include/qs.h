@@ -138,7 +138,8 @@ int qs_set_grid_limit(qs_state* s, int max_workgroups);
  *                        pass's op list as it runs;
  *   QS_EXEC_COMPILED     each pass gets its own straight-line kernel,
  *                        generated from its op list and compiled at run time
- *                        (hipRTC) the first time a pass of that shape runs,
+ *                        (ROCm clang, or hipRTC; see qs_precompile) the
+ *                        first time a pass of that shape runs,
  *                        then cached for the process: the same circuit form
  *                        with other matrices or angles runs without
  *                        compiling again;

@@ -1,4 +1,5 @@
-// qs_jit.cpp -- fused passes compiled per pass shape at run time (hipRTC).
+// qs_jit.cpp -- fused passes compiled per pass shape at run time (ROCm
+// clang in child processes, or hipRTC).
 //
 // The planner (qs_plan.cpp) turns a block of gates into a list of fused ops
 // over a register tile (qHiPSTER Sec. 4.4, Fig. 4: one memory round trip per
