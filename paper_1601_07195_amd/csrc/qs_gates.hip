@@ -225,25 +225,46 @@ Status hip_status(hipError_t e, const char* what) {
 
 static Status last_launch(const char* what) { return hip_status(hipGetLastError(), what); }
 
+// Occupancy cap of the streaming gate kernels, in waves per SIMD (0: none),
+// applied as dynamic LDS that no kernel reads: a workgroup of `block`
+// threads that already holds `static_lds` bytes gets enough more that at
+// most the capped number of workgroups share a CU's 160 KiB.  Fewer
+// workgroups in flight measured faster on the paired streams (fewer DRAM
+// rows open at once), by 3-13 % at most targets; the exchange kernels
+// (targets below unit bit 8, 256-thread workgroups) measured slower with
+// any cap and run uncapped.  QS_STREAM_WAVES, when set, replaces the cap of
+// every streaming launch (0: none), to measure it.
+constexpr size_t kCuLds = 160 * 1024;
+static size_t stream_lds(int block, size_t static_lds, int waves) {
+  if (const char* e = getenv("QS_STREAM_WAVES"))
+    if (*e) waves = atoi(e);
+  if (waves <= 0) return 0;
+  const int wg_waves = (block + 63) / 64;
+  const int wgs = std::max(1, (waves * 4) / wg_waves);  // 4 SIMDs per CU
+  const size_t per = (kCuLds / (size_t)wgs) & ~(size_t)511;  // 512-byte allocation granules
+  return per > static_lds ? per - static_lds : 0;
+}
+
 template <typename R, typename T, int CM, int MAP>
-static void go_pair(StateImpl* s, uint64_t count, int t, int c, const Mat<R>& q) {
+static void go_pair(StateImpl* s, uint64_t count, int t, int c, const Mat<R>& q, int waves) {
   hipLaunchKernelGGL((k_pair<R, T, kPairBlock, CM, MAP>), dim3(grid_for(count, kPairBlock)),
-                     dim3(kPairBlock), 0, s->stream, (T*)s->ptr, count, t, c, q);
+                     dim3(kPairBlock), stream_lds(kPairBlock, 0, waves), s->stream, (T*)s->ptr, count, t, c, q);
 }
 // Exchange kernel; t is the target's bit in the work index (< 8).
 template <typename R, typename T, int CM>
 static void go_exchange(StateImpl* s, uint64_t count, int t, int c, const Mat<R>& q) {
   if (t < kShflBits)
     hipLaunchKernelGGL((k_exchange<R, T, kShflBlock, CM, false>), dim3(grid_for(count, kShflBlock)),
-                       dim3(kShflBlock), 0, s->stream, (T*)s->ptr, count, t, c, q);
+                       dim3(kShflBlock), stream_lds(kShflBlock, 0, 0), s->stream, (T*)s->ptr, count, t, c, q);
   else
     hipLaunchKernelGGL((k_exchange<R, T, kShflBlock, CM, true>), dim3(grid_for(count, kShflBlock)),
-                       dim3(kShflBlock), 0, s->stream, (T*)s->ptr, count, t, c, q);
+                       dim3(kShflBlock), stream_lds(kShflBlock, kShflBlock * sizeof(T), 0), s->stream, (T*)s->ptr,
+                       count, t, c, q);
 }
 template <int CM>
 static void go_inner(StateImpl* s, uint64_t count, int c, const Mat<float>& q) {
   hipLaunchKernelGGL((k_inner<kShflBlock, CM>), dim3(grid_for(count, kShflBlock)),
-                     dim3(kShflBlock), 0, s->stream, (f4*)s->ptr, count, c, q);
+                     dim3(kShflBlock), stream_lds(kShflBlock, 0, 0), s->stream, (f4*)s->ptr, count, c, q);
 }
 
 Status launch_init_basis(StateImpl* s, uint64_t index) {
@@ -268,20 +289,28 @@ Status launch_init_basis(StateImpl* s, uint64_t index) {
 // (and a grid of control/target pairs) at n = 30 on MI355X.
 constexpr int kExchangeBits = 8;  // target bits handled inside a 256-lane workgroup
 
-// Block order of the paired-stream kernel for a single-qubit gate on unit
-// bit t of a 2^u-unit state (units of 16 bytes: complex128 amplitudes,
-// complex64 pairs): 1 (consecutive blocks spread over the XCDs) where it
-// measured faster than the plain order.  From a sweep of every target with
-// both orders at u = 30..33, each size at both amplitude types, which
-// agreed in unit bits: u <= 30: bits 22-23; u = 31: 8, 22-23; u = 32: 8,
-// 21-23; u = 33 (128 GiB states): 17-27, where the plain order
-// loses up to 9 %.
+// Block order and occupancy cap of the paired-stream kernel for a
+// single-qubit gate on unit bit t (>= 8) of a 2^u-unit state (units of 16
+// bytes: complex128 amplitudes, complex64 pairs).  From a sweep of every
+// target over both block orders (plain, or consecutive blocks spread over
+// the XCDs) and caps of none, 3 and 4 waves per SIMD at u = 30..33, with
+// the u = 30 results repeated at complex64 (which agreed in unit bits):
+// three waves per SIMD in the plain order is best or within 1 % nearly
+// everywhere; four is 2-3 % better at bits 18-19 and 25-28 up to u = 32;
+// the spread order is better at bits 20-22 (20-23 at u = 33), the pair
+// distances of 16-128 MiB where the plain order dips most.
 static int pair_block_order(int u, int t) {
-  if (u >= 33) return (t >= 17 && t <= 27) ? 1 : 0;
-  if (u == 32) return (t == 8 || (t >= 21 && t <= 23)) ? 1 : 0;
-  if (u == 31) return (t == 8 || t == 22 || t == 23) ? 1 : 0;
-  return (t == 22 || t == 23) ? 1 : 0;
+  if (u >= 33) return (t >= 20 && t <= 23) ? 1 : 0;
+  return (t >= 20 && t <= 22) ? 1 : 0;
 }
+static int pair_waves_1q(int u, int t) {
+  if (u >= 33) return 3;
+  return (t == 18 || t == 19 || (t >= 25 && t <= 28)) ? 4 : 3;
+}
+// Controlled gates on the paired streams: three waves per SIMD measured
+// faster at most (control, target) pairs of a sweep (up to 21 % with the
+// control inside a line, 4-11 % outside).
+constexpr int kPairWavesCU = 3;
 
 // QS_1Q_BLOCK_ORDER (0 or 1), when set, forces the block order of the
 // paired-stream kernel for every target (to measure both); otherwise
@@ -300,8 +329,9 @@ static void units_1q(StateImpl* s, int u, int t, const Mat<R>& q) {
     return;
   }
   const int forced = block_order_env();
-  if ((forced >= 0 ? forced : pair_block_order(u, t)) == 1) go_pair<R, T, kNone, 1>(s, 1ull << (u - 1), t, 0, q);
-  else go_pair<R, T, kNone, 0>(s, 1ull << (u - 1), t, 0, q);
+  const int w = pair_waves_1q(u, t);
+  if ((forced >= 0 ? forced : pair_block_order(u, t)) == 1) go_pair<R, T, kNone, 1>(s, 1ull << (u - 1), t, 0, q, w);
+  else go_pair<R, T, kNone, 0>(s, 1ull << (u - 1), t, 0, q, w);
 }
 
 // QS_CU_COMPACT_FROM (0..3), when set, is the lowest control unit bit that
@@ -336,10 +366,10 @@ static void units_cu(StateImpl* s, int u, int c, int t, const Mat<R>& q) {
     if (compact) go_exchange<R, T, kCompact>(s, 1ull << (u - 1), t < c ? t : t - 1, c, q);
     else go_exchange<R, T, kPred>(s, 1ull << u, t, c, q);
   } else if (compact) {
-    if (c < kExchangeBits) go_pair<R, T, kCompact, 1>(s, 1ull << (u - 2), t, c, q);
-    else go_pair<R, T, kCompact, 0>(s, 1ull << (u - 2), t, c, q);
+    if (c < kExchangeBits) go_pair<R, T, kCompact, 1>(s, 1ull << (u - 2), t, c, q, kPairWavesCU);
+    else go_pair<R, T, kCompact, 0>(s, 1ull << (u - 2), t, c, q, kPairWavesCU);
   } else {
-    go_pair<R, T, kPred, 0>(s, 1ull << (u - 1), t, c, q);
+    go_pair<R, T, kPred, 0>(s, 1ull << (u - 1), t, c, q, kPairWavesCU);
   }
 }
 
@@ -388,7 +418,7 @@ Status launch_apply_cu(StateImpl* s, int c, int t, const double* q) {
   } else if (c == 0) {  // control inside each unit: update odd amplitudes only
     const int tv = t - 1;
     if (tv < kExchangeBits) go_exchange<float, f4, kInnerCtrl>(s, 1ull << u, tv, 0, m);
-    else go_pair<float, f4, kInnerCtrl, 0>(s, 1ull << (u - 1), tv, 0, m);
+    else go_pair<float, f4, kInnerCtrl, 0>(s, 1ull << (u - 1), tv, 0, m, kPairWavesCU);
   } else {
     units_cu<float, f4>(s, u, c - 1, t - 1, m);
   }
