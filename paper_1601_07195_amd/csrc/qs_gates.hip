@@ -48,6 +48,7 @@ constexpr int kShflBits = 6;  // lane bits of a wave64
 constexpr int kLineUnitBits = 3;  // 128-byte line = 8 units
 constexpr int kPairBlock = 64;
 constexpr int kShflBlock = 256;
+constexpr int kShflWave = 64;  // one-wave workgroups for the shuffle exchange
 
 // Logical workgroup index.  MAP 0: as dispatched.  MAP 1: XCD-contiguous --
 // dispatch slot b runs on XCD b % 8, so logical block (b % 8) * (G / 8) +
@@ -250,10 +251,23 @@ static void go_pair(StateImpl* s, uint64_t count, int t, int c, const Mat<R>& q,
   hipLaunchKernelGGL((k_pair<R, T, kPairBlock, CM, MAP>), dim3(grid_for(count, kPairBlock)),
                      dim3(kPairBlock), stream_lds(kPairBlock, 0, waves), s->stream, (T*)s->ptr, count, t, c, q);
 }
+// Whether `count` work items fit one-wave workgroups in a one-shot grid (no
+// grid-stride iterations: grid_for caps a launch at 2^31 work items).  The
+// shuffle exchange and the complex64 qubit-0 kernel then run one-wave
+// workgroups, which measured 4-5 % faster than 256-thread ones at 2^28-2^31
+// work items (two or four units per thread, and any occupancy cap,
+// measured slower); with grid-stride iterations they measured slower, so
+// larger launches keep 256 threads.  The LDS exchange needs its partner
+// wave in the workgroup.
+static bool one_wave_groups(uint64_t count) { return count <= (1ull << 31); }
+
 // Exchange kernel; t is the target's bit in the work index (< 8).
 template <typename R, typename T, int CM>
 static void go_exchange(StateImpl* s, uint64_t count, int t, int c, const Mat<R>& q) {
-  if (t < kShflBits)
+  if (t < kShflBits && one_wave_groups(count))
+    hipLaunchKernelGGL((k_exchange<R, T, kShflWave, CM, false>), dim3(grid_for(count, kShflWave)),
+                       dim3(kShflWave), stream_lds(kShflWave, 0, 0), s->stream, (T*)s->ptr, count, t, c, q);
+  else if (t < kShflBits)
     hipLaunchKernelGGL((k_exchange<R, T, kShflBlock, CM, false>), dim3(grid_for(count, kShflBlock)),
                        dim3(kShflBlock), stream_lds(kShflBlock, 0, 0), s->stream, (T*)s->ptr, count, t, c, q);
   else
@@ -263,8 +277,12 @@ static void go_exchange(StateImpl* s, uint64_t count, int t, int c, const Mat<R>
 }
 template <int CM>
 static void go_inner(StateImpl* s, uint64_t count, int c, const Mat<float>& q) {
-  hipLaunchKernelGGL((k_inner<kShflBlock, CM>), dim3(grid_for(count, kShflBlock)),
-                     dim3(kShflBlock), stream_lds(kShflBlock, 0, 0), s->stream, (f4*)s->ptr, count, c, q);
+  if (one_wave_groups(count))
+    hipLaunchKernelGGL((k_inner<kShflWave, CM>), dim3(grid_for(count, kShflWave)),
+                       dim3(kShflWave), stream_lds(kShflWave, 0, 0), s->stream, (f4*)s->ptr, count, c, q);
+  else
+    hipLaunchKernelGGL((k_inner<kShflBlock, CM>), dim3(grid_for(count, kShflBlock)),
+                       dim3(kShflBlock), stream_lds(kShflBlock, 0, 0), s->stream, (f4*)s->ptr, count, c, q);
 }
 
 Status launch_init_basis(StateImpl* s, uint64_t index) {
