@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stddef.h>
+#include <stdlib.h>
 #include <stdint.h>
 
 #include <string>
@@ -104,6 +105,10 @@ Status launch_expect(StateImpl* s, const PauliTable& t, double* out_host);
 // dst = H src (asynchronous).
 Status launch_apply_pauli_sum(StateImpl* src, StateImpl* dst, const PauliTable& t);
 // max_i |a_i - b_i| for b a device state of a's shape (synchronises).
+// Dynamic LDS bytes that cap a streaming launch of `block`-thread
+// workgroups (already holding `static_lds` bytes) at `waves` waves per
+// SIMD (0: no cap); QS_STREAM_WAVES, when set, replaces `waves`.
+size_t stream_lds(int block, size_t static_lds, int waves);
 Status max_abs_diff(StateImpl* a, const void* b, double* out_host);
 // <a|b> into device double2 at dev_out (asynchronous).
 Status launch_inner_dev(StateImpl* a, StateImpl* b, double* dev_out);
