@@ -242,7 +242,8 @@ size_t stream_lds(int block, size_t static_lds, int waves) {
   if (waves <= 0) return 0;
   const int wg_waves = (block + 63) / 64;
   const int wgs = std::max(1, (waves * 4) / wg_waves);  // 4 SIMDs per CU
-  const size_t per = (kCuLds / (size_t)wgs) & ~(size_t)511;  // 512-byte allocation granules
+  // 512-byte allocation granules; at most 64 KiB per workgroup
+  const size_t per = std::min<size_t>(kCuLds / (size_t)wgs, 64 * 1024) & ~(size_t)511;
   return per > static_lds ? per - static_lds : 0;
 }
 
