@@ -9,12 +9,12 @@
 // j + 1 (complex64); complex64 qubit 0 lies inside a unit.
 //
 // Three access shapes, picked per gate from its qubits:
-//   * exchange (target unit bit < 8): a 256-lane workgroup reads 256
-//     consecutive units, one per lane; each lane fetches its partner from lane
-//     ^ 2^t with a cross-lane shuffle (bit < 6, same wavefront) or through LDS
-//     (bits 6, 7), so both members of every pair arrive in one contiguous
-//     4 KiB access;
-//   * paired streams (target unit bit >= 8): lane p handles the pair
+//   * exchange (single-qubit target unit bit < 7, controlled < 8): a
+//     workgroup reads consecutive units, one per lane; each lane fetches its
+//     partner from lane ^ 2^t with a cross-lane shuffle (bit < 6, same
+//     wavefront) or through LDS (bits 6, 7), so both members of every pair
+//     arrive in one contiguous access;
+//   * paired streams (higher targets): lane p handles the pair
 //     (i0, i0 + 2^t), i0 = p with a 0 inserted at bit t; consecutive lanes
 //     read two contiguous 1 KiB runs;
 //   * in-unit (complex64 target qubit 0): each unit holds a whole pair.
@@ -27,12 +27,14 @@
 // of scattering half-line accesses.
 //
 // Launch shape: 16 bytes per lane per stream, 64-lane workgroups for the
-// paired-stream kernel and 256-lane workgroups for the exchange kernels (the
-// fastest measured on MI355X), grid-stride loops with the grid capped so the
-// dispatch never exceeds 2^31 work-items.  Workgroups are dispatched to the
-// 8 XCDs round-robin; for some strides the paired-stream kernel is faster
-// when each XCD walks one contiguous eighth of the work ("XCD-contiguous"
-// order), which the dispatch rules below select from a measured sweep.
+// paired-stream kernel and the shuffle exchange (256 lanes for the LDS
+// exchange and for launches too large for a one-shot grid), grid-stride
+// loops with the grid capped so the dispatch never exceeds 2^31 work-items.
+// The paired streams run with an occupancy cap (fewer workgroups in flight
+// measured faster on HBM).  Workgroups are dispatched to the 8 XCDs
+// round-robin; for some strides the paired-stream kernel is faster when
+// each XCD walks one contiguous eighth of the work ("XCD-contiguous"
+// order).  The dispatch rules below come from measured sweeps.
 #include <algorithm>
 #include <cstdlib>
 
