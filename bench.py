@@ -92,8 +92,10 @@ def workload_only(args) -> None:
         ops = {"circuit": lambda: C.random_circuit(n, args.circuit_gates, np.random.default_rng(C.SEED_BASE + 1)),
                "qft": lambda: C.qft_circuit(n), "iqft": lambda: C.iqft_circuit(n)}[w]().ops
         st = Q.State(n, dtype)
-        st.run(ops)
-        torch.cuda.synchronize()
+        # two untimed runs: kernels compiled, then both tile orders timed
+        for _ in range(2):
+            st.run(ops)
+            torch.cuda.synchronize()
         log(f"[bench] {w} n={n} {args.dtype}: warmup done")
         st.run(ops)
         torch.cuda.synchronize()
@@ -123,7 +125,7 @@ def workload_only(args) -> None:
         circ, ham = C.workload_ansatz(n, 20, 100)
         st = Q.State(n, dtype)
         lam = Q.State(n, dtype, init=False)
-        for _ in range(2):
+        for _ in range(3):
             st.init_basis(0)
             Q.grad_adjoint(st, lam, circ.ops, circ.theta, ham.codes, ham.coeff)
             torch.cuda.synchronize()
@@ -373,11 +375,14 @@ def oracle_workloads(np, C, O, threads: int) -> dict:
 
 
 def timed(fn, stream, reps=1):
-    """Mean seconds of fn() over reps, with HIP events on `stream` after one
-    untimed call."""
+    """Mean seconds of fn() over reps, with HIP events on `stream` after two
+    untimed calls: the first compiles the pass kernels, and each compiled
+    pass times one tile order in the first call and the other in the second,
+    so the timed calls run the faster one."""
     import torch
-    fn()
-    torch.cuda.synchronize()
+    for _ in range(2):
+        fn()
+        torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
@@ -597,8 +602,9 @@ def adjoint_section(Q, C, np, torch, ps_pairs):
             st.init_basis(0)
             return Q.qs_grad_adjoint(st.handle, circ.ops, circ.theta, x, z, ham.coeff, lam.handle)
 
-        adj()
-        torch.cuda.synchronize()
+        for _ in range(2):  # compile, then both tile orders timed
+            adj()
+            torch.cuda.synchronize()
         t0 = time.perf_counter()
         reps = 3 if n == 20 else 1
         for _ in range(reps):
@@ -611,8 +617,9 @@ def adjoint_section(Q, C, np, torch, ps_pairs):
             return Q.qs_expect_pauli(st.handle, x, z, ham.coeff)
 
         pairs = P if n == 20 else min(ps_pairs, P)
-        energy(circ.theta)
-        torch.cuda.synchronize()
+        for _ in range(2):  # both tile orders timed before the timed loop
+            energy(circ.theta)
+            torch.cuda.synchronize()
         t0 = time.perf_counter()
         gps = np.zeros(pairs)
         for j in range(pairs):
@@ -695,7 +702,7 @@ def sweep_split(Q, torch, np, n, circ, x, z, coeff, dtype, st, lam, stream, reps
     fwd, _, _ = Q.qs_plan(n, dtype, circ.ops, circ.theta)
     rev, _, _ = Q.qs_plan(n, dtype, circ.ops, circ.theta, flags=Q.QS_PLAN_ADJOINT_REVERSE)
     tf, th, tr = [], [], []
-    for i in range(reps + 1):
+    for i in range(reps + 2):
         st.init_basis(0)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -709,7 +716,7 @@ def sweep_split(Q, torch, np, n, circ, x, z, coeff, dtype, st, lam, stream, reps
         t0 = time.perf_counter()
         Q.qs_grad_adjoint(st.handle, circ.ops, circ.theta, x, z, coeff, lam.handle, Q.QS_ADJ_STATE_IS_FINAL)
         t1 = time.perf_counter()
-        if i > 0:  # the first round compiles
+        if i > 1:  # the first round compiles, the first two time the tile orders
             tf.append(e0.elapsed_time(e1) * 1e-3)
             th.append(e1.elapsed_time(e2) * 1e-3)
             tr.append(t1 - t0)
@@ -899,6 +906,11 @@ def main():
             st.run(circ.ops)
             st.probabilities()
 
+    # compiled passes time each tile order on their first two launches and
+    # keep the faster: two untimed runs of the circuit before the warmup
+    for _ in range(2):
+        st.run(circ.ops)
+        torch.cuda.synchronize()
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()

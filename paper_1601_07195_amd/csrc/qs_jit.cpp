@@ -117,6 +117,18 @@ __device__ __forceinline__ double qs_row_sum16(double v) {
 #define QS_CMUL(PR, PI, DR, DI) { const R t_ = PR * (DR) - PI * (DI); PI = PR * (DI) + PI * (DR); PR = t_; }
 // Im(conj(l) w)
 #define QS_IMC(LR, LI, WR, WI) ((double)(LR) * (double)(WI) - (double)(LI) * (double)(WR))
+// Tile of workgroup b in a grid of one workgroup per tile: b itself (order
+// 0), or, in order 1, with dispatch slot b (which runs on XCD b % 8) taken
+// so that each XCD walks one contiguous eighth of the tiles; a tail of
+// ntiles % 8 keeps its index.  Any other grid walks the tiles in order.
+__device__ __forceinline__ unsigned long long qs_tile_of(unsigned long long b, unsigned long long ntiles,
+                                                         unsigned order) {
+  if (order == 1 && (unsigned long long)gridDim.x == ntiles) {
+    const unsigned long long per = ntiles >> 3;
+    if (b < per * 8) return (b & 7) * per + (b >> 3);
+  }
+  return b;
+}
 )";
 
 // Tile-bit layout of one pass (the same values the interpreter receives in
@@ -548,7 +560,7 @@ class PassEmitter {
       src_("        const int lb_ = (int)h_->m[1];");
       src_("        const double* tlo = (const double*)(maps + (unsigned long long)h_->m[0]);");
       src_("        const double* thi = tlo + 2 * (1ull << lb_);");
-      src_("        const unsigned long long lo = tile & ((1ull << lb_) - 1ull), hi = tile >> lb_;");
+      src_("        const unsigned long long lo = tix & ((1ull << lb_) - 1ull), hi = tix >> lb_;");
       src_("        QS_CMUL(pr, pi, (R)tlo[2 * lo], (R)tlo[2 * lo + 1])");
       src_("        QS_CMUL(pr, pi, (R)thi[2 * hi], (R)thi[2 * hi + 1])");
       src_("      }");
@@ -775,11 +787,11 @@ class PassEmitter {
     src_.s += kNamePlaceholder;
     if (adj_)
       src_("(%s* __restrict__ qa, %s* __restrict__ ql, const QsOp* __restrict__ ops, const char* __restrict__ maps, "
-           "double* __restrict__ part, unsigned long long ntiles) {",
+           "double* __restrict__ part, unsigned long long ntiles, unsigned order) {",
            VT, VT);
     else
       src_("(%s* __restrict__ qa, const QsOp* __restrict__ ops, const char* __restrict__ maps, "
-           "unsigned long long ntiles) {",
+           "unsigned long long ntiles, unsigned order) {",
            VT);
     src_("  typedef %s R;", g_.c64 ? "float" : "double");
     src_("  const int tid = threadIdx.x;");
@@ -799,7 +811,8 @@ class PassEmitter {
     src_("  R xr[%d], xi[%d];", g_.RA, g_.RA);
     if (adj_) src_("  R yr[%d], yi[%d];", g_.RA, g_.RA);
     src_("  for (unsigned long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {");
-    emit_base("base", "tile");
+    src_("    const unsigned long long tix = qs_tile_of(tile, ntiles, order);");
+    emit_base("base", "tix");
     // per-thread phase-run tables: read before this iteration's tile loads
     // so that waiting for them never waits for the tile
     for (int i = p_.op_first; i < p_.op_first + p_.nops; ++i) {
@@ -863,7 +876,9 @@ class PassEmitter {
       src_("  if (tid < %d) {", ngrad);
       src_("    double s = 0.0;");
       src_("    for (int r = 0; r < 16; ++r) s += acc[tid * 16 + r];");
-      src_("    part[(unsigned long long)tid * gridDim.x + blockIdx.x] = s;");
+      // indexed by tile, so that the sum over partials is the same in either
+      // tile order
+      src_("    part[(unsigned long long)tid * gridDim.x + qs_tile_of(blockIdx.x, ntiles, order)] = s;");
       src_("  }");
     }
     src_("}");
