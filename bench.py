@@ -92,8 +92,8 @@ def workload_only(args) -> None:
         ops = {"circuit": lambda: C.random_circuit(n, args.circuit_gates, np.random.default_rng(C.SEED_BASE + 1)),
                "qft": lambda: C.qft_circuit(n), "iqft": lambda: C.iqft_circuit(n)}[w]().ops
         st = Q.State(n, dtype)
-        # two untimed runs: kernels compiled, then both tile orders timed
-        for _ in range(2):
+        # untimed runs: kernels compiled, then every tile order timed
+        for _ in range(TUNE_CALLS):
             st.run(ops)
             torch.cuda.synchronize()
         log(f"[bench] {w} n={n} {args.dtype}: warmup done")
@@ -125,7 +125,7 @@ def workload_only(args) -> None:
         circ, ham = C.workload_ansatz(n, 20, 100)
         st = Q.State(n, dtype)
         lam = Q.State(n, dtype, init=False)
-        for _ in range(3):
+        for _ in range(TUNE_CALLS + 1):
             st.init_basis(0)
             Q.grad_adjoint(st, lam, circ.ops, circ.theta, ham.codes, ham.coeff)
             torch.cuda.synchronize()
@@ -374,13 +374,18 @@ def oracle_workloads(np, C, O, threads: int) -> dict:
     return out
 
 
-def timed(fn, stream, reps=1):
-    """Mean seconds of fn() over reps, with HIP events on `stream` after two
-    untimed calls: the first compiles the pass kernels, and each compiled
-    pass times one tile order in the first call and the other in the second,
-    so the timed calls run the faster one."""
+# Compiled fused passes time each of their tile orders (eight at the sizes
+# timed here) on one launch apiece before keeping the fastest: this many
+# untimed calls precede every timed fused run.
+TUNE_CALLS = 8
+
+
+def timed(fn, stream, reps=1, warm=1):
+    """Mean seconds of fn() over reps, with HIP events on `stream` after
+    `warm` untimed calls (TUNE_CALLS for fused runs, so that the timed calls
+    run each compiled pass in its chosen tile order)."""
     import torch
-    for _ in range(2):
+    for _ in range(warm):
         fn()
         torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -419,7 +424,7 @@ def large_section(Q, C, np, torch):
         for cname, qc in (("qft", C.qft_circuit(n)), ("iqft", C.iqft_circuit(n))):
             pg = sum((S if op["kind"] == C.OP_CU else 2 * S) for op in qc.ops)
             qi, _, _ = Q.qs_plan(n, dtype, qc.ops)
-            tf = timed(lambda: st.run(qc.ops), stream, 1)
+            tf = timed(lambda: st.run(qc.ops), stream, 1, warm=TUNE_CALLS)
             top[cname] = {"gates": len(qc), "passes_fused": qi["passes"], "fused_s": round(tf, 4),
                           "fused_hbm_GBps": round(qi["hbm_bytes"] / tf / 1e9, 1),
                           "fused_effective_GBps": round(pg / tf / 1e9, 1)}
@@ -435,12 +440,12 @@ def large_section(Q, C, np, torch):
         circ = C.workload_circuit_qft(n)
         info, _, _ = Q.qs_plan(n, dtype, circ.ops)
         pergate = sum((S if op["kind"] == C.OP_CU else 2 * S) for op in circ.ops)
-        tc = timed(lambda: st.run(circ.ops), stream, 1)
+        tc = timed(lambda: st.run(circ.ops), stream, 1, warm=TUNE_CALLS)
         winfo, _, _ = Q.qs_plan(n, dtype, circ.ops, flags=Q.QS_RUN_WIDE_TILES)
-        tw = timed(lambda: st.run(circ.ops, wide=True), stream, 1)
+        tw = timed(lambda: st.run(circ.ops, wide=True), stream, 1, warm=TUNE_CALLS)
         qft = C.qft_circuit(n)
         qinfo, _, _ = Q.qs_plan(n, dtype, qft.ops)
-        tq = timed(lambda: st.run(qft.ops), stream, 1)
+        tq = timed(lambda: st.run(qft.ops), stream, 1, warm=TUNE_CALLS)
         out[f"n{n}_{name}"] = {
             "state_bytes": S,
             "one_qubit_GBps_by_target": one,
@@ -481,7 +486,7 @@ def qft_section(Q, C, np, torch):
                 pergate = sum((S if op["kind"] == C.OP_CU else 2 * S) for op in circ.ops)
                 info, _, _ = Q.qs_plan(n, dtype, circ.ops)
                 reps = 3 if n <= 24 else 1
-                tf = timed(lambda: st.run(circ.ops), stream, reps)
+                tf = timed(lambda: st.run(circ.ops), stream, reps, warm=TUNE_CALLS)
                 rec[cname] = {
                     "gates": len(circ), "passes_fused": info["passes"], "fused_s": round(tf, 5),
                     "fused_effective_GBps": round(pergate / tf / 1e9, 1),
@@ -569,13 +574,13 @@ def reorder_section(Q, C, np, torch, n):
         out["permute"][label] = rec
     for label, ops in (("random1000", C.random_circuit(n, 1000, np.random.default_rng(C.SEED_BASE + 1)).ops),
                        ("random500_qft", C.workload_circuit_qft(n, 500).ops)):
-        t_plain = timed(lambda: st.run(ops), stream, 1)
+        t_plain = timed(lambda: st.run(ops), stream, 1, warm=TUNE_CALLS)
         info = {}
 
         def reordered():
             info.update(st.run_reordered(ops, n - 3))
 
-        t_re = timed(reordered, stream, 1)
+        t_re = timed(reordered, stream, 1, warm=TUNE_CALLS)
         out["runs"][label] = {"plain_ms": round(t_plain * 1e3, 1), "reordered_ms": round(t_re * 1e3, 1),
                               "upper_qubits": 3, **info}
     del st
@@ -602,7 +607,7 @@ def adjoint_section(Q, C, np, torch, ps_pairs):
             st.init_basis(0)
             return Q.qs_grad_adjoint(st.handle, circ.ops, circ.theta, x, z, ham.coeff, lam.handle)
 
-        for _ in range(2):  # compile, then both tile orders timed
+        for _ in range(TUNE_CALLS):  # compile, then every tile order timed
             adj()
             torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -617,7 +622,7 @@ def adjoint_section(Q, C, np, torch, ps_pairs):
             return Q.qs_expect_pauli(st.handle, x, z, ham.coeff)
 
         pairs = P if n == 20 else min(ps_pairs, P)
-        for _ in range(2):  # both tile orders timed before the timed loop
+        for _ in range(TUNE_CALLS):  # tile orders timed before the timed loop
             energy(circ.theta)
             torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -702,7 +707,7 @@ def sweep_split(Q, torch, np, n, circ, x, z, coeff, dtype, st, lam, stream, reps
     fwd, _, _ = Q.qs_plan(n, dtype, circ.ops, circ.theta)
     rev, _, _ = Q.qs_plan(n, dtype, circ.ops, circ.theta, flags=Q.QS_PLAN_ADJOINT_REVERSE)
     tf, th, tr = [], [], []
-    for i in range(reps + 2):
+    for i in range(reps + TUNE_CALLS):
         st.init_basis(0)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -716,7 +721,7 @@ def sweep_split(Q, torch, np, n, circ, x, z, coeff, dtype, st, lam, stream, reps
         t0 = time.perf_counter()
         Q.qs_grad_adjoint(st.handle, circ.ops, circ.theta, x, z, coeff, lam.handle, Q.QS_ADJ_STATE_IS_FINAL)
         t1 = time.perf_counter()
-        if i > 1:  # the first round compiles, the first two time the tile orders
+        if i >= TUNE_CALLS:  # the first rounds compile and time the tile orders
             tf.append(e0.elapsed_time(e1) * 1e-3)
             th.append(e1.elapsed_time(e2) * 1e-3)
             tr.append(t1 - t0)
@@ -906,9 +911,9 @@ def main():
             st.run(circ.ops)
             st.probabilities()
 
-    # compiled passes time each tile order on their first two launches and
-    # keep the faster: two untimed runs of the circuit before the warmup
-    for _ in range(2):
+    # compiled passes time each tile order on one of their first launches
+    # and keep the fastest: untimed runs of the circuit before the warmup
+    for _ in range(TUNE_CALLS):
         st.run(circ.ops)
         torch.cuda.synchronize()
     for _ in range(args.warmup):
@@ -947,7 +952,7 @@ def main():
     # the same circuit with wide tiles (fewer low qubits fixed per tile:
     # fewer passes, each at a lower fraction of peak)
     wide_info, _, _ = Q.qs_plan(n, dtype, circ.ops, flags=Q.QS_RUN_WIDE_TILES)
-    t_wide = timed(lambda: st.run(circ.ops, wide=True), stream, 3)
+    t_wide = timed(lambda: st.run(circ.ops, wide=True), stream, 3, warm=TUNE_CALLS)
 
     # STREAM copy (B_mem, Sec. 5.2) on a 2 x 4 GiB pair of buffers
     cs = 4 << 30

@@ -722,20 +722,23 @@ bool use_compiled_passes(const StateImpl* s) {
 // once decides which addresses are in flight together, and so how its
 // accesses spread over HBM channels and banks; it changes no result (each
 // tile is computed the same way, and gradient partials are kept per tile).
-// Over the passes of random circuits and the QFT at n = 30 (complex128) and
-// 31 (complex64), the XCD-spread order (order 1) was faster than the plain
-// one on about half of the passes and slower on the rest, by up to 1.5 ms
-// of 6-8 ms, the same way in repeated runs, with no rule on the tile's
-// qubits that predicted it well (a fit on the held qubits recovered half
-// the gain).  So a compiled kernel times each order once, on its first two
-// launches at a tile count, with events around the launch that are read at
-// a later launch once they have completed, and then keeps the faster: one
-// timed sample per order picked within 0.1 % of the per-pass best.
-// QS_TILE_ORDER (plain, spread), when set, fixes the order instead.
+// Order k splits the tiles into 2^k regions that consecutive workgroups
+// walk side by side (k = 0: plain; k = 3: one eighth per XCD).  Traced pass
+// by pass over random circuits and the QFT at n = 30 (complex128) and 31
+// (complex64), the fastest k differed from pass to pass, by up to 1.5 ms of
+// 6-8 ms, the same way in repeated runs, and no rule on the tile's qubits
+// predicted it well.  So a compiled kernel times each order once, one per
+// launch at a tile count, with events around the launch that are read at a
+// later launch once they have completed, and then keeps the fastest.
+// Picking from one timed sample per order of k = 0..7 and scoring on
+// another run took 5.9 % (complex128) and 3.7 % (complex64) off the random
+// circuit against the plain order alone.  QS_TILE_ORDER = k (0..7), when
+// set, fixes the order instead.
+constexpr int kTileOrders = 8;
 struct TileOrderStats {
   hipEvent_t start = nullptr, stop = nullptr;
-  int pending = -1;          // order of the timed launch not yet read
-  float ms[2] = {-1.f, -1.f};
+  int pending = -1;  // order of the timed launch not yet read
+  float ms[kTileOrders] = {-1.f, -1.f, -1.f, -1.f, -1.f, -1.f, -1.f, -1.f};
 };
 static std::mutex g_order_mu;
 static std::map<std::tuple<int, hipFunction_t, uint64_t>, TileOrderStats> g_orders;
@@ -743,9 +746,16 @@ static std::map<std::tuple<int, hipFunction_t, uint64_t>, TileOrderStats> g_orde
 static int forced_tile_order() {
   const char* e = getenv("QS_TILE_ORDER");
   if (!e || !*e) return -1;
-  if (!strcmp(e, "plain")) return 0;
-  if (!strcmp(e, "spread")) return 1;
-  return -1;
+  const int k = atoi(e);
+  return k >= 0 && k < kTileOrders ? k : -1;
+}
+
+// Orders that differ from one another at ntiles (a power of two): 2^k
+// regions of at least two tiles each.
+static int tile_orders_at(uint64_t ntiles) {
+  int k = 0;
+  while (k < kTileOrders && (ntiles >> k) >= 2) ++k;
+  return k;
 }
 
 // Launch a compiled pass kernel; args: the kernel's arguments in order, the
@@ -761,8 +771,9 @@ static Status launch_compiled(StateImpl* s, const JitPass& jp, unsigned grid, ui
   };
   *order = 0;
   const int forced = forced_tile_order();
-  // the orders differ only on a one-shot grid of at least two tiles per XCD
-  if (forced >= 0 || grid != ntiles || ntiles < 16) {
+  // the orders differ only on a one-shot grid of several tiles
+  const int norders = tile_orders_at(ntiles);
+  if (forced >= 0 || grid != ntiles || norders < 2) {
     if (forced >= 0) *order = (unsigned)forced;
     return launch();
   }
@@ -786,12 +797,17 @@ static Status launch_compiled(StateImpl* s, const JitPass& jp, unsigned grid, ui
       o.pending = -1;  // the sample is lost; the order is timed again
     }
   }
-  const bool known = o.ms[0] >= 0.f && o.ms[1] >= 0.f;
-  if (known || o.pending >= 0 || cap != hipStreamCaptureStatusNone) {
-    *order = known && o.ms[1] < o.ms[0] ? 1u : 0u;
+  // next: the lowest order not yet timed; best: the fastest timed (0 if none)
+  int next = -1, best = 0;
+  for (int k = norders - 1; k >= 0; --k) {
+    if (o.ms[k] < 0.f) next = k;
+    else if (o.ms[best] < 0.f || o.ms[k] <= o.ms[best]) best = k;
+  }
+  if (next < 0 || o.pending >= 0 || cap != hipStreamCaptureStatusNone) {
+    *order = (unsigned)best;
     return launch();
   }
-  *order = o.ms[0] < 0.f ? 0u : 1u;
+  *order = (unsigned)next;
   if (!o.start && (hipEventCreate(&o.start) != hipSuccess || hipEventCreate(&o.stop) != hipSuccess)) {
     (void)hipGetLastError();
     return launch();  // no events: no timing, order 0

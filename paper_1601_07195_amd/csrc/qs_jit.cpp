@@ -117,15 +117,18 @@ __device__ __forceinline__ double qs_row_sum16(double v) {
 #define QS_CMUL(PR, PI, DR, DI) { const R t_ = PR * (DR) - PI * (DI); PI = PR * (DI) + PI * (DR); PR = t_; }
 // Im(conj(l) w)
 #define QS_IMC(LR, LI, WR, WI) ((double)(LR) * (double)(WI) - (double)(LI) * (double)(WR))
-// Tile of workgroup b in a grid of one workgroup per tile: b itself (order
-// 0), or, in order 1, with dispatch slot b (which runs on XCD b % 8) taken
-// so that each XCD walks one contiguous eighth of the tiles; a tail of
-// ntiles % 8 keeps its index.  Any other grid walks the tiles in order.
+// Tile of workgroup b in a grid of one workgroup per tile: with order k,
+// the tiles form 2^k contiguous regions and dispatch slot b takes tile
+// b >> k of region b mod 2^k, so consecutive slots (which the dispatcher
+// deals round-robin to the 8 XCDs) walk 2^k regions side by side; k = 0
+// is the plain order, k = 3 gives each XCD its own eighth.  Tile counts are
+// powers of two; any other grid walks the tiles in order.
 __device__ __forceinline__ unsigned long long qs_tile_of(unsigned long long b, unsigned long long ntiles,
                                                          unsigned order) {
-  if (order == 1 && (unsigned long long)gridDim.x == ntiles) {
-    const unsigned long long per = ntiles >> 3;
-    if (b < per * 8) return (b & 7) * per + (b >> 3);
+  if (order > 0 && order < 32 && (unsigned long long)gridDim.x == ntiles && (ntiles >> order) > 0 &&
+      (ntiles & ((1ull << order) - 1ull)) == 0) {
+    const unsigned long long per = ntiles >> order;
+    return (b & ((1ull << order) - 1ull)) * per + (b >> order);
   }
   return b;
 }

@@ -1,7 +1,8 @@
-"""Tile order of compiled passes: the plain order, the XCD-spread order and
-the tuner that times both and keeps the faster must give bit-identical
-states and gradients (the order only decides which workgroup takes which
-tile), and those must match the oracle within the usual bounds."""
+"""Tile order of compiled passes: every order (2^k regions of tiles walked
+side by side) and the tuner that times them and keeps the fastest must give
+bit-identical states and gradients (the order only decides which workgroup
+takes which tile), and those must match the oracle within the usual
+bounds."""
 from __future__ import annotations
 
 import math
@@ -15,17 +16,19 @@ from tests.gpu_util import Q, random_state, rounded_input, to_gpu_state  # noqa:
 
 pytestmark = pytest.mark.gpu
 
-# "" leaves the order to the tuner: its first run times order 0, the second
-# (after the first has completed) order 1, the third takes the faster
-ORDERS = ("plain", "spread", "", "", "")
+# forced orders k = 0..4, then "" (the tuner): each run times the next
+# order (each run ends with a host copy, so the last timing has completed),
+# until every order the tile count allows (at most five at 32 tiles) is
+# timed; the runs after that take the fastest
+ORDERS = ("0", "1", "2", "3", "4") + ("",) * 7
 
 
 def dt(Q, name):
     return Q.QS_C128 if name == "c128" else Q.QS_C64
 
 
-# 16 and 32 tiles of 2^11 (complex128) or 2^12 (complex64) amplitudes: the
-# smallest sizes at which the two orders differ
+# 16 and 32 tiles of 2^11 (complex128) or 2^12 (complex64) amplitudes:
+# four and five distinct orders
 @pytest.mark.parametrize("name,n", [("c128", 15), ("c128", 16), ("c64", 16), ("c64", 17)])
 def test_tile_orders_forward(Q, name, n, monkeypatch):
     monkeypatch.setenv("QS_FUSED_EXEC", "compiled")
