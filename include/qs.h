@@ -151,6 +151,13 @@ int qs_set_grid_limit(qs_state* s, int max_workgroups);
  * operations inside a pass may differ).  A pass the generator does not take
  * runs interpreted.  Compilation needs no GPU (see qs_precompile); its cost
  * is reported by qs_jit_stats.
+ * Compiled passes also choose their tile order, that is which workgroup
+ * takes which tile: 2^k regions of the tiles walked side by side,
+ * k = 0..7.  Each order the tile count allows is timed on one launch, with
+ * HIP events on the state's stream that are read at a later launch once
+ * complete.  From then on, for the rest of the process, that kernel at that
+ * tile count uses the fastest order.  The order changes no result bit.  The
+ * environment variable QS_TILE_ORDER=k fixes the order instead.
  * Errors: QS_EINVAL (bad state or mode).
  */
 #define QS_EXEC_AUTO 0
