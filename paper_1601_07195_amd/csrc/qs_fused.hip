@@ -9,6 +9,7 @@
 // bits become register bits; diagonal gates scale each amplitude by the
 // entry its target bit selects, wherever that bit lives (register, thread
 // index, or outside the tile).
+#include <float.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -784,17 +785,28 @@ static Status launch_compiled(StateImpl* s, const JitPass& jp, unsigned grid, ui
   }
   std::lock_guard<std::mutex> lock(g_order_mu);
   TileOrderStats& o = g_orders[std::make_tuple(s->device, f, ntiles)];
+  // Timing never fails a run: if the events cannot be made, recorded or
+  // read, the orders not yet timed are dropped and the kernel keeps the
+  // fastest timed order (plain if none).
+  auto stop_timing = [&]() {
+    (void)hipGetLastError();
+    for (int k = 0; k < kTileOrders; ++k)
+      if (o.ms[k] < 0.f) o.ms[k] = FLT_MAX;
+  };
   if (o.pending >= 0) {
     const hipError_t q = hipEventQuery(o.stop);
     if (q == hipSuccess) {
       float ms = 0.f;
-      if (hipEventElapsedTime(&ms, o.start, o.stop) == hipSuccess) o.ms[o.pending] = ms;
+      const int k = o.pending;
       o.pending = -1;
+      if (hipEventElapsedTime(&ms, o.start, o.stop) == hipSuccess) o.ms[k] = ms;
+      else stop_timing();
     } else if (q == hipErrorNotReady) {
       // not an error: keep the runtime's last-error state clean of it
       if (hipPeekAtLastError() == hipErrorNotReady) (void)hipGetLastError();
     } else {
-      o.pending = -1;  // the sample is lost; the order is timed again
+      o.pending = -1;
+      stop_timing();
     }
   }
   // next: the lowest order not yet timed; best: the fastest timed (0 if none)
@@ -807,17 +819,29 @@ static Status launch_compiled(StateImpl* s, const JitPass& jp, unsigned grid, ui
     *order = (unsigned)best;
     return launch();
   }
-  *order = (unsigned)next;
-  if (!o.start && (hipEventCreate(&o.start) != hipSuccess || hipEventCreate(&o.stop) != hipSuccess)) {
-    (void)hipGetLastError();
-    return launch();  // no events: no timing, order 0
+  if (!o.start) {
+    // the events belong to the state's device
+    int cur = -1;
+    bool ok = hipGetDevice(&cur) == hipSuccess && (cur == s->device || hipSetDevice(s->device) == hipSuccess);
+    ok = ok && hipEventCreate(&o.start) == hipSuccess;
+    ok = ok && hipEventCreate(&o.stop) == hipSuccess;
+    if (cur >= 0 && cur != s->device) (void)hipSetDevice(cur);
+    if (!ok) {
+      stop_timing();
+      *order = (unsigned)best;
+      return launch();
+    }
   }
-  st = hip_status(hipEventRecord(o.start, s->stream), "tile order timing");
-  if (!st.good()) return st;
+  *order = (unsigned)next;
+  if (hipEventRecord(o.start, s->stream) != hipSuccess) {
+    stop_timing();
+    *order = (unsigned)best;
+    return launch();
+  }
   st = launch();
   if (!st.good()) return st;
-  st = hip_status(hipEventRecord(o.stop, s->stream), "tile order timing");
-  if (st.good()) o.pending = (int)*order;
+  if (hipEventRecord(o.stop, s->stream) != hipSuccess) stop_timing();
+  else o.pending = (int)*order;
   return st;
 }
 
