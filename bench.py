@@ -42,6 +42,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0  # MI355X HBM3E, AMD published peak
+# Compiled fused passes time each of their tile orders (eight at the sizes
+# timed here) on one launch apiece before keeping the fastest: this many
+# untimed calls precede every timed fused run.
+TUNE_CALLS = 8
 
 
 def parse():
@@ -372,12 +376,6 @@ def oracle_workloads(np, C, O, threads: int) -> dict:
     out["note"] = "extrapolated entries: time of 10 gates (n = 28) or one energy (n = 20) times the gate or sweep count"
     del psi
     return out
-
-
-# Compiled fused passes time each of their tile orders (eight at the sizes
-# timed here) on one launch apiece before keeping the fastest: this many
-# untimed calls precede every timed fused run.
-TUNE_CALLS = 8
 
 
 def timed(fn, stream, reps=1, warm=1):
